@@ -1,0 +1,194 @@
+/*
+ * btd.h -- C ABI of the MI355X (gfx950) decomposition-method solver for
+ * block-tridiagonal systems (Belov, Nugumanov & Yakovlev,
+ * "Decomposition method for block-tridiagonal matrix systems",
+ * arXiv:1505.06864).
+ *
+ * The system (Sec. 2, Eq. eq01, written here with A diagonal, B
+ * sub-diagonal and C super-diagonal, which are the paper's C, A and B):
+ *
+ *     B_i X_{i-1} + A_i X_i + C_i X_{i+1} = F_i,    i = 0 .. N-1,
+ *
+ * with M x M blocks A_i, B_i, C_i and M x R blocks X_i, F_i.  B_0 and C_{N-1}
+ * are never read.
+ *
+ * Method (Sec. 2): P-1 separator block rows split the other rows into P
+ * subsystems.  Each subsystem is eliminated independently by the block
+ * Thomas algorithm (Sec. 3; here block LU with partial pivoting inside
+ * every diagonal block, triangular solves and Schur-complement products),
+ * which yields its part z of the solution and its two spikes Z_L, Z_R
+ * (Eq. e231).  The coupling system of P-1 block rows (Eqs. e2311, e232) is
+ * solved by the Thomas algorithm or, when depth >= 1, by the same method
+ * applied recursively (Sec. 4.2, Eq. DMrec1).  The subsystem rows are then
+ * recovered as X = z - Z_L h^{k-1} - Z_R h^k (Eq. endSolution).
+ *
+ * Conventions for every entry point:
+ *   - Matrix and vector pointers are DEVICE pointers (HBM of the current
+ *     HIP device), FP64, row-major.  A, B, C: [N][M][M] (block i at
+ *     offset i*M*M).  F, X: [N][M][R] (block row i is an M x R row-major
+ *     tile at offset i*M*R).
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     All work is enqueued asynchronously on that stream; the calls return
+ *     once the work is enqueued.
+ *   - The library never allocates device memory.  The caller provides the
+ *     workspaces, sized by btd_workspace_bytes, and keeps them alive.
+ *   - Return value 0 = enqueued.  A negative value -k means that argument k
+ *     (1-based position in the call) is invalid; it is detected on the host
+ *     before anything is enqueued, and nothing is enqueued then.
+ *     BTD_ERR_LAUNCH means a HIP launch failed (work enqueued before it may
+ *     still run).  Numerical failures are found on the device and read back
+ *     with btd_get_info after the stream has been synchronised.
+ *   - Calls on one plan are not thread-safe; distinct plans may be used on
+ *     distinct streams concurrently.
+ */
+#ifndef BTD_H
+#define BTD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes (btd_get_info, btd_status_string, call returns). */
+#define BTD_OK 0
+#define BTD_ERR_SINGULAR 1   /* an exactly zero pivot in the LU of a diagonal block D_i */
+#define BTD_ERR_NONFINITE 2  /* a pivot that is NaN or infinite                          */
+#define BTD_ERR_LAUNCH 3     /* a HIP launch or copy failed (returned by the call)       */
+
+#define BTD_PREC_F64 0
+
+/* Largest block size the kernels accept (diagonal-block LU panel held in LDS). */
+#define BTD_MAX_M 512
+
+typedef struct btd_plan_s *btd_plan_t;
+
+/*
+ * Problem description.
+ *   N         block rows, N >= 1.
+ *   M         block size, 1 <= M <= BTD_MAX_M.
+ *   P         number of subsystems, 1 <= P and 2P-1 <= N when P > 1
+ *             (every subsystem keeps at least one row; Sec. 2 places the
+ *             separators anywhere from the second to the next-to-last row).
+ *             P = 1 is the plain block Thomas algorithm (Sec. 3).
+ *   depth     DM levels applied to the coupling system (0 = Thomas
+ *             algorithm, Eq. e232; d >= 1 = DM with m subsystems, Eq.
+ *             DMrec1, m from Eq. SuppMatrM: m = round(sqrt(P/3 (5 + 2/(1 +
+ *             R/M)))) capped at floor(P/3), at least 2; levels whose
+ *             coupling system has fewer than 3 rows use the Thomas
+ *             algorithm).  R here is max_nrhs.
+ *   prec      BTD_PREC_F64.
+ *   max_nrhs  largest R a later btd_solve may use (>= 1).
+ *   seps      NULL for the equal split (subsystem sizes floor((N-P+1)/P),
+ *             the first (N-P+1) mod P subsystems one row longer), or a HOST
+ *             array of P-1 strictly increasing 0-based separator rows with
+ *             1 <= q, q <= N-2 and at least one row between neighbours.
+ *             Copied during btd_factor; not retained.
+ */
+typedef struct {
+    int32_t N, M, P, depth, prec, max_nrhs;
+    const int32_t *seps;
+} btd_desc_t;
+
+/*
+ * Workspace sizes in bytes for a description.  factor_ws holds the LU
+ * factors, pivots, E_i = D_i^{-1} C_i, the spikes and the coupling
+ * system(s); it lives as long as the plan.  solve_ws is scratch for one
+ * btd_solve (or btd_solve_batch) call with up to max_nrhs columns.
+ * Returns 0 or -1 (invalid description).  Either output pointer may be NULL.
+ */
+int btd_workspace_bytes(const btd_desc_t *desc, size_t *factor_ws, size_t *solve_ws);
+
+/*
+ * Factor (Sec. 2 steps up to and including the coupling-system factor):
+ * for every subsystem the block LU of D_i = A_i - B_i E_{i-1}, E_i and both
+ * spikes; the coupling matrix H - W_L S^{-1} W_R (Eq. e2311) and its own
+ * factorisation.  A, B, C are BORROWED by the plan (btd_residual and later
+ * solves read them): keep them unchanged and allocated until
+ * btd_plan_destroy.  factor_ws (>= factor bytes, 256-byte aligned) is
+ * owned by the plan until btd_plan_destroy.  *out receives a host-side plan
+ * handle (a small host allocation).
+ * Returns 0; -1 invalid description or seps; -2/-3/-4 NULL A/B/C; -5 NULL or
+ * not 256-byte-aligned factor_ws; -6 factor_bytes too small; -8 NULL out;
+ * BTD_ERR_LAUNCH.
+ */
+int btd_factor(const btd_desc_t *desc, const double *A, const double *B, const double *C,
+               void *factor_ws, size_t factor_bytes, void *stream, btd_plan_t *out);
+
+/*
+ * Solve with a factored plan (Sec. 2, Eqs. e231 (RHS part), e2311 (vector
+ * part), e232, endSolution): X = A^{-1} F for nrhs columns,
+ * 1 <= nrhs <= max_nrhs.  F and X are [N][M][nrhs]; X may equal F (in
+ * place).  solve_ws (>= solve bytes, 256-byte aligned) is scratch for the
+ * duration of the call on `stream`.
+ * Returns 0; -1 NULL plan; -2 nrhs out of range; -3/-4 NULL F/X; -5 NULL or
+ * misaligned solve_ws; -6 solve_bytes too small; BTD_ERR_LAUNCH.
+ */
+int btd_solve(btd_plan_t plan, int32_t nrhs, const double *F, double *X, void *solve_ws,
+              size_t solve_bytes, void *stream);
+
+/*
+ * Solve several factored systems in one call: for s < count,
+ * X[s] = A_s^{-1} F[s] with nrhs[s] columns.  plans, nrhs, F, X are HOST
+ * arrays of length count (F[s], X[s] device pointers).  The solves run one
+ * after another on `stream` sharing solve_ws, which must be at least the
+ * largest solve size of the plans.
+ * Returns 0; -1 count < 0 or a NULL array; -(1000 + s) for the first bad
+ * entry s (NULL plan or pointer, nrhs out of range); -6 NULL, misaligned or
+ * too small solve_ws; BTD_ERR_LAUNCH.
+ */
+int btd_solve_batch(int32_t count, const btd_plan_t *plans, const int32_t *nrhs,
+                    const double *const *F, double *const *X, void *solve_ws, size_t solve_bytes,
+                    void *stream);
+
+/*
+ * Relative residual per column (the check of a solve; not a step of the
+ * paper): out[c] = ||F[:,c] - (A X)[:,c]||_2 / ||F[:,c]||_2, or the
+ * unscaled norm when F[:,c] = 0.  A, B, C, X, F are device pointers, out is
+ * a DEVICE array of R doubles, work a DEVICE array of at least
+ * btd_residual_work_bytes(N, M, R) bytes.
+ * Returns 0; -1 bad sizes; -k for the first NULL pointer argument k
+ * (4..10); BTD_ERR_LAUNCH.
+ */
+size_t btd_residual_work_bytes(int32_t N, int32_t M, int32_t R);
+int btd_residual(int32_t N, int32_t M, int32_t R, const double *A, const double *B, const double *C,
+                 const double *X, const double *F, double *out, void *work, void *stream);
+
+/*
+ * Numerical status of the last btd_factor of `plan`; call after
+ * synchronising the factor's stream.  *status = BTD_OK, BTD_ERR_SINGULAR or
+ * BTD_ERR_NONFINITE; *block_row = 0-based row i of the first failing D_i
+ * (a separator row when the failure was in the coupling system), *col = its
+ * pivot column; both -1 when OK.  Any output pointer may be NULL.  Performs
+ * a blocking device-to-host copy.  Returns 0, -1 for a NULL plan, or
+ * BTD_ERR_LAUNCH when the copy fails.
+ */
+int btd_get_info(btd_plan_t plan, int32_t *status, int32_t *block_row, int32_t *col);
+
+/* Separator rows actually used (P-1 entries into a host array). Returns 0 or -1. */
+int btd_plan_separators(btd_plan_t plan, int32_t *seps_out);
+
+/* Subsystem count used for the coupling system at recursion level `level`
+ * (level 0 = the top system's P).  Returns the count, or -1 past the last level. */
+int btd_plan_level_parts(btd_plan_t plan, int32_t level);
+
+/* Host-only helpers (no device work): the equal-split separator rows for
+ * (N, P) written into seps_out[P-1], and the subsystem count the recursive
+ * coupling solve uses for P subsystems, block size M and R columns (Eq.
+ * SuppMatrM rule described for btd_desc_t::depth; 1 = Thomas algorithm).
+ * Both return -1 for invalid sizes. */
+int btd_default_separators(int32_t N, int32_t P, int32_t *seps_out);
+int btd_default_coupling_parts(int32_t P, int32_t M, int32_t R);
+
+/* Releases the host handle.  The caller then owns factor_ws and A, B, C
+ * again; enqueued work that uses them must have finished first. */
+void btd_plan_destroy(btd_plan_t plan);
+
+/* Static string for a status or argument-error code. */
+const char *btd_status_string(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BTD_H */

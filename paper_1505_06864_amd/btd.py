@@ -1,0 +1,254 @@
+"""Python binding of libbtd.so (include/btd.h): argument marshalling only.
+
+Every step of the factor and the solve runs in the library's HIP kernels;
+this module converts torch tensors to device pointers, allocates the
+workspaces the C ABI asks for (torch owns all device memory), and passes the
+current HIP stream.  There is no CPU fallback: without the built library on
+a HIP device the calls raise.
+
+Shapes (row-major, torch.float64 on a HIP device): A, B, C (N, M, M) --
+diagonal, sub-diagonal, super-diagonal blocks of
+B_i X_{i-1} + A_i X_i + C_i X_{i+1} = F_i; F, X (N, M, R).
+"""
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbtd.so")
+
+BTD_OK, BTD_ERR_SINGULAR, BTD_ERR_NONFINITE, BTD_ERR_LAUNCH = 0, 1, 2, 3
+BTD_PREC_F64 = 0
+BTD_MAX_M = 512
+
+# Every symbol include/btd.h declares.
+EXPORTS = ("btd_workspace_bytes", "btd_factor", "btd_solve", "btd_solve_batch", "btd_residual_work_bytes",
+           "btd_residual", "btd_get_info", "btd_plan_separators", "btd_plan_level_parts",
+           "btd_default_separators", "btd_default_coupling_parts", "btd_plan_destroy", "btd_status_string")
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int32), ("M", ctypes.c_int32), ("P", ctypes.c_int32),
+                ("depth", ctypes.c_int32), ("prec", ctypes.c_int32), ("max_nrhs", ctypes.c_int32),
+                ("seps", ctypes.POINTER(ctypes.c_int32))]
+
+
+_lib = None
+
+
+def lib():
+    """Load libbtd.so (raises when it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1505_06864_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, sz, i32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32
+        L.btd_workspace_bytes.argtypes = [ctypes.POINTER(Desc), ctypes.POINTER(sz), ctypes.POINTER(sz)]
+        L.btd_factor.argtypes = [ctypes.POINTER(Desc), vp, vp, vp, vp, sz, vp, ctypes.POINTER(vp)]
+        L.btd_solve.argtypes = [vp, i32, vp, vp, vp, sz, vp]
+        L.btd_solve_batch.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(i32), ctypes.POINTER(vp),
+                                      ctypes.POINTER(vp), vp, sz, vp]
+        L.btd_residual_work_bytes.argtypes = [i32, i32, i32]
+        L.btd_residual_work_bytes.restype = sz
+        L.btd_residual.argtypes = [i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.btd_get_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        L.btd_plan_separators.argtypes = [vp, ctypes.POINTER(i32)]
+        L.btd_plan_level_parts.argtypes = [vp, i32]
+        L.btd_default_separators.argtypes = [i32, i32, ctypes.POINTER(i32)]
+        L.btd_default_coupling_parts.argtypes = [i32, i32, i32]
+        L.btd_plan_destroy.argtypes = [vp]
+        L.btd_plan_destroy.restype = None
+        L.btd_status_string.argtypes = [ctypes.c_int]
+        L.btd_status_string.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+class BtdError(RuntimeError):
+    def __init__(self, code, what):
+        msg = lib().btd_status_string(code).decode()
+        super().__init__(f"{what}: code {code} ({msg})")
+        self.code = code
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _check(t, name, shape=None):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or t.device.type != "cuda":
+        raise TypeError(f"{name} must be a torch.float64 tensor on a HIP device")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous (row-major)")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
+def _stream_handle(stream, device):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream(device)
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _aligned_buffer(nbytes, device):
+    """A torch uint8 buffer and a 256-byte-aligned pointer inside it."""
+    torch = _torch()
+    buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    ptr = (buf.data_ptr() + 255) // 256 * 256
+    return buf, ptr
+
+
+def make_desc(N, M, P=1, depth=0, max_nrhs=1, seps=None):
+    d = Desc(N, M, P, depth, BTD_PREC_F64, max_nrhs, None)
+    keep = None
+    if seps is not None:
+        keep = (ctypes.c_int32 * max(len(seps), 1))(*[int(q) for q in seps])
+        d.seps = ctypes.cast(keep, ctypes.POINTER(ctypes.c_int32))
+    return d, keep
+
+
+def workspace_bytes(N, M, P=1, depth=0, max_nrhs=1, seps=None):
+    """(factor bytes, solve bytes) for a description; raises on an invalid one."""
+    d, _keep = make_desc(N, M, P, depth, max_nrhs, seps)
+    f, s = ctypes.c_size_t(), ctypes.c_size_t()
+    rc = lib().btd_workspace_bytes(ctypes.byref(d), ctypes.byref(f), ctypes.byref(s))
+    if rc != BTD_OK:
+        raise BtdError(rc, "btd_workspace_bytes")
+    return f.value, s.value
+
+
+def default_separators(N, P):
+    """Equal-split separator rows the library uses when none are given (host only)."""
+    out = (ctypes.c_int32 * max(P - 1, 1))()
+    rc = lib().btd_default_separators(N, P, out)
+    if rc != BTD_OK:
+        raise BtdError(rc, "btd_default_separators")
+    return [out[k] for k in range(P - 1)]
+
+
+def default_coupling_parts(P, M, R):
+    """Subsystem count of the recursive coupling solve (host only)."""
+    rc = lib().btd_default_coupling_parts(P, M, R)
+    if rc < 0:
+        raise BtdError(rc, "btd_default_coupling_parts")
+    return rc
+
+
+class Plan:
+    """A factored system (btd_factor).  Keeps A, B, C and the factor workspace alive."""
+
+    def __init__(self, A, B, C, P=1, depth=0, max_nrhs=1, seps=None, stream=None):
+        N, M = A.shape[0], A.shape[1]
+        for t, n in ((A, "A"), (B, "B"), (C, "C")):
+            _check(t, n, (N, M, M))
+        self.N, self.M, self.P, self.depth, self.max_nrhs = N, M, P, depth, max_nrhs
+        self.device = A.device
+        self.A, self.B, self.C = A, B, C
+        fbytes, self.solve_bytes = workspace_bytes(N, M, P, depth, max_nrhs, seps)
+        self._ws, ptr = _aligned_buffer(fbytes, A.device)
+        d, _keep = make_desc(N, M, P, depth, max_nrhs, seps)
+        h = ctypes.c_void_p()
+        rc = lib().btd_factor(ctypes.byref(d), A.data_ptr(), B.data_ptr(), C.data_ptr(), ptr, fbytes,
+                              _stream_handle(stream, A.device), ctypes.byref(h))
+        if rc != BTD_OK:
+            raise BtdError(rc, "btd_factor")
+        self._h = h
+        self.factor_bytes = fbytes
+
+    @property
+    def handle(self):
+        return self._h
+
+    def solve(self, F, X=None, stream=None):
+        """X = A^{-1} F (X may be F for an in-place solve).  Returns X."""
+        R = F.shape[2]
+        _check(F, "F", (self.N, self.M, R))
+        if X is None:
+            X = _torch().empty_like(F)
+        _check(X, "X", (self.N, self.M, R))
+        buf, ptr = _aligned_buffer(self.solve_bytes, F.device)
+        rc = lib().btd_solve(self._h, R, F.data_ptr(), X.data_ptr(), ptr, self.solve_bytes,
+                             _stream_handle(stream, F.device))
+        if rc != BTD_OK:
+            raise BtdError(rc, "btd_solve")
+        self._last_solve_ws = buf  # lives until the next solve on this plan (stream-ordered reuse)
+        return X
+
+    def info(self):
+        """(status, block_row, col) of the factor; synchronises the device first."""
+        _torch().cuda.synchronize(self.device)
+        st, row, col = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        rc = lib().btd_get_info(self._h, ctypes.byref(st), ctypes.byref(row), ctypes.byref(col))
+        if rc != BTD_OK:
+            raise BtdError(rc, "btd_get_info")
+        return st.value, row.value, col.value
+
+    def separators(self):
+        out = (ctypes.c_int32 * max(self.P - 1, 1))()
+        lib().btd_plan_separators(self._h, out)
+        return [out[k] for k in range(self.P - 1)]
+
+    def level_parts(self):
+        parts, lvl = [], 0
+        while True:
+            p = lib().btd_plan_level_parts(self._h, lvl)
+            if p < 0:
+                return parts
+            parts.append(p)
+            lvl += 1
+
+    def destroy(self):
+        if getattr(self, "_h", None):
+            _torch().cuda.synchronize(self.device)
+            lib().btd_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def factor(A, B, C, P=1, depth=0, max_nrhs=1, seps=None, stream=None):
+    return Plan(A, B, C, P=P, depth=depth, max_nrhs=max_nrhs, seps=seps, stream=stream)
+
+
+def solve_batch(plans, Fs, Xs=None, stream=None):
+    """btd_solve_batch over several plans; returns the list of solutions."""
+    torch = _torch()
+    n = len(plans)
+    if Xs is None:
+        Xs = [torch.empty_like(F) for F in Fs]
+    nbytes = max(p.solve_bytes for p in plans) if n else 256
+    buf, ptr = _aligned_buffer(nbytes, Fs[0].device if n else "cuda")
+    hp = (ctypes.c_void_p * max(n, 1))(*[p.handle.value for p in plans])
+    nr = (ctypes.c_int32 * max(n, 1))(*[F.shape[2] for F in Fs])
+    fp = (ctypes.c_void_p * max(n, 1))(*[F.data_ptr() for F in Fs])
+    xp = (ctypes.c_void_p * max(n, 1))(*[X.data_ptr() for X in Xs])
+    rc = lib().btd_solve_batch(n, hp, nr, fp, xp, ptr, nbytes,
+                               _stream_handle(stream, Fs[0].device if n else None))
+    if rc != BTD_OK:
+        raise BtdError(rc, "btd_solve_batch")
+    torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+    del buf
+    return Xs
+
+
+def residual(A, B, C, X, F, stream=None):
+    """Per-column ||F - A X||_2 / ||F||_2 computed on the device (tensor of R float64)."""
+    torch = _torch()
+    N, M, R = F.shape
+    for t, nm in ((A, "A"), (B, "B"), (C, "C")):
+        _check(t, nm, (N, M, M))
+    _check(X, "X", (N, M, R))
+    _check(F, "F", (N, M, R))
+    out = torch.empty(R, dtype=torch.float64, device=F.device)
+    work = torch.empty(max(lib().btd_residual_work_bytes(N, M, R), 8) // 8, dtype=torch.float64, device=F.device)
+    rc = lib().btd_residual(N, M, R, A.data_ptr(), B.data_ptr(), C.data_ptr(), X.data_ptr(), F.data_ptr(),
+                            out.data_ptr(), work.data_ptr(), _stream_handle(stream, F.device))
+    if rc != BTD_OK:
+        raise BtdError(rc, "btd_residual")
+    return out

@@ -1,0 +1,391 @@
+// btd_plan.cpp -- host side of the C ABI (include/btd.h): argument checks,
+// partition, workspace layout, and the launch sequence of the decomposition
+// method (arXiv:1505.06864, Sec. 2) over the recursion levels.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "btd_internal.h"
+
+namespace {
+
+using btd::KArgs;
+using btd::Level;
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct LevelPlan {
+    int N = 0, M = 0, P = 1, nmax = 0;
+    std::vector<int> sep;  // P+1 entries: -1, q_0 .. q_{P-2}, N
+    size_t off_LU = 0, off_DI = 0, off_W = 0, off_Z = 0, off_Hd = 0, off_Hb = 0, off_Hc = 0;
+    size_t off_perm = 0, off_sep = 0;
+};
+
+// Equal split: subsystem sizes floor((N-P+1)/P), the first (N-P+1) mod P one row longer.
+void equal_split(int N, int P, std::vector<int>& sep) {
+    sep.assign(P + 1, 0);
+    sep[0] = -1;
+    sep[P] = N;
+    const int rows = N - (P - 1), base = rows / P, rem = rows % P;
+    int pos = 0;
+    for (int k = 0; k < P - 1; ++k) {
+        pos += base + (k < rem ? 1 : 0);
+        sep[k + 1] = pos;
+        pos += 1;
+    }
+}
+
+// Subsystem count of the coupling system for a recursive level
+// (Eq. SuppMatrM, capped at floor(P/3), at least 2; 1 = Thomas algorithm).
+int coupling_parts(int P, int M, int R) {
+    if (P - 1 < 3) return 1;
+    const double ms = std::sqrt((double)P / 3.0 * (5.0 + 2.0 / (1.0 + (double)R / (double)M)));
+    int m = (int)std::floor(ms + 0.5);
+    if (m > P / 3) m = P / 3;
+    if (m < 2) m = 2;
+    return m;
+}
+
+bool valid_desc(const btd_desc_t* d) {
+    if (!d) return false;
+    if (d->N < 1 || d->M < 1 || d->M > BTD_MAX_M || d->P < 1 || d->depth < 0 || d->max_nrhs < 1) return false;
+    if (d->prec != BTD_PREC_F64) return false;
+    if (d->P > 1 && 2 * (int64_t)d->P - 1 > d->N) return false;
+    if (d->N > (1 << 24) - 1) return false;
+    if (d->seps && d->P > 1) {
+        int prev = -1;
+        for (int k = 0; k < d->P - 1; ++k) {
+            const int q = d->seps[k];
+            if (q <= prev + 1 || q < 1 || q > d->N - 2) return false;
+            prev = q;
+        }
+        if (d->N - 1 - prev < 1) return false;
+    }
+    return true;
+}
+
+// Level list and factor-workspace layout for a description.
+size_t build_levels(const btd_desc_t* d, std::vector<LevelPlan>& lv) {
+    lv.clear();
+    size_t off = align_up(sizeof(unsigned long long));  // status word first
+    int N = d->N, P = d->P, depth = d->depth;
+    const int M = d->M;
+    const size_t MM = (size_t)M * M;
+    const size_t nblk = (size_t)(M + 15) / 16;
+    bool top = true;
+    while (true) {
+        LevelPlan L;
+        L.N = N; L.M = M; L.P = P;
+        if (top && d->seps && P > 1) {
+            L.sep.assign(P + 1, 0);
+            L.sep[0] = -1;
+            L.sep[P] = N;
+            for (int k = 0; k < P - 1; ++k) L.sep[k + 1] = d->seps[k];
+        } else {
+            equal_split(N, P, L.sep);
+        }
+        L.nmax = 0;
+        for (int k = 0; k < P; ++k) {
+            const int nk = L.sep[k + 1] - L.sep[k] - 1;
+            if (nk > L.nmax) L.nmax = nk;
+        }
+        L.off_LU = off; off = align_up(off + sizeof(double) * N * MM);
+        L.off_DI = off; off = align_up(off + sizeof(double) * N * nblk * 512);
+        L.off_W = off; off = align_up(off + sizeof(double) * N * MM * 2);
+        if (P > 1) {
+            L.off_Z = off; off = align_up(off + sizeof(double) * N * MM * 2);
+            L.off_Hd = off; off = align_up(off + sizeof(double) * (P - 1) * MM);
+            L.off_Hb = off; off = align_up(off + sizeof(double) * (P - 1) * MM);
+            L.off_Hc = off; off = align_up(off + sizeof(double) * (P - 1) * MM);
+        }
+        L.off_perm = off; off = align_up(off + sizeof(int) * (size_t)N * M);
+        L.off_sep = off; off = align_up(off + sizeof(int) * (size_t)(P + 1));
+        lv.push_back(L);
+        if (P == 1) break;
+        const int Nc = P - 1;
+        const int Pc = (depth > 0) ? coupling_parts(P, M, d->max_nrhs) : 1;
+        N = Nc;
+        P = Pc;
+        depth = depth > 0 ? depth - 1 : 0;
+        top = false;
+    }
+    return off;
+}
+
+size_t solve_bytes_for(const std::vector<LevelPlan>& lv, int R) {
+    size_t off = 0;
+    for (const auto& L : lv)
+        if (L.P > 1) off = align_up(off + sizeof(double) * (size_t)(L.P - 1) * L.M * R);
+    return off > 0 ? off : kAlign;
+}
+
+bool g_configured = false;
+
+}  // namespace
+
+struct btd_plan_s {
+    btd_desc_t desc;
+    std::vector<LevelPlan> levels;
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    const double *A = nullptr, *B = nullptr, *C = nullptr;
+    unsigned long long* status = nullptr;
+
+    Level level_dev(int l) const {
+        const LevelPlan& L = levels[l];
+        Level d;
+        if (l == 0) { d.A = A; d.B = B; d.C = C; }
+        else {
+            const LevelPlan& up = levels[l - 1];
+            d.A = (const double*)(ws + up.off_Hd);
+            d.B = (const double*)(ws + up.off_Hb);
+            d.C = (const double*)(ws + up.off_Hc);
+        }
+        d.LU = (double*)(ws + L.off_LU);
+        d.DI = (double*)(ws + L.off_DI);
+        d.W = (double*)(ws + L.off_W);
+        d.Z = L.P > 1 ? (double*)(ws + L.off_Z) : nullptr;
+        d.Hd = L.P > 1 ? (double*)(ws + L.off_Hd) : nullptr;
+        d.Hb = L.P > 1 ? (double*)(ws + L.off_Hb) : nullptr;
+        d.Hc = L.P > 1 ? (double*)(ws + L.off_Hc) : nullptr;
+        d.perm = (int*)(ws + L.off_perm);
+        d.sep = (const int*)(ws + L.off_sep);
+        d.N = L.N; d.M = L.M; d.P = L.P; d.level = l;
+        return d;
+    }
+};
+
+namespace {
+
+#define BTD_TRY(x)                                     \
+    do {                                               \
+        hipError_t e_ = (x);                           \
+        if (e_ != hipSuccess) return BTD_ERR_LAUNCH;   \
+    } while (0)
+
+int enqueue_factor(btd_plan_s* p, hipStream_t s) {
+    BTD_TRY(btd::launch_init_status(p->status, s));
+    for (size_t l = 0; l < p->levels.size(); ++l) {
+        const LevelPlan& LP = p->levels[l];
+        KArgs ka;
+        std::memset(&ka, 0, sizeof(ka));
+        ka.L = p->level_dev((int)l);
+        ka.status = p->status;
+        BTD_TRY(btd::launch_write_ints((int*)(p->ws + LP.off_sep), LP.sep.data(), LP.P + 1, s));
+        for (int t = 0; t < LP.nmax; ++t) {
+            ka.step = t;
+            BTD_TRY(btd::launch_fwd_gemm(ka, s));
+            BTD_TRY(btd::launch_getrf(ka, s));
+            BTD_TRY(btd::launch_getrs(ka, false, s));
+        }
+        if (LP.P > 1) {
+            for (int t = 0; t < LP.nmax; ++t) {
+                ka.step = t;
+                BTD_TRY(btd::launch_bwd_gemm(ka, s));
+            }
+            BTD_TRY(btd::launch_couple(ka, s));
+        }
+    }
+    return BTD_OK;
+}
+
+// Solve level l in place on X (which already holds F when l > 0).
+int enqueue_solve_level(const btd_plan_s* p, size_t l, int R, const double* F, double* X, char* sws,
+                        size_t sws_off, hipStream_t s) {
+    const LevelPlan& LP = p->levels[l];
+    KArgs ka;
+    std::memset(&ka, 0, sizeof(ka));
+    ka.L = p->level_dev((int)l);
+    ka.R = R;
+    ka.F = F;
+    ka.X = X;
+    ka.status = p->status;
+    for (int t = 0; t < LP.nmax; ++t) {
+        ka.step = t;
+        BTD_TRY(btd::launch_rhs_fwd(ka, s));
+        BTD_TRY(btd::launch_getrs(ka, true, s));
+    }
+    for (int t = 1; t < LP.nmax; ++t) {
+        ka.step = t;
+        BTD_TRY(btd::launch_rhs_bwd(ka, s));
+    }
+    if (LP.P > 1) {
+        double* Fc = (double*)(sws + sws_off);
+        const size_t next = align_up(sws_off + sizeof(double) * (size_t)(LP.P - 1) * LP.M * R);
+        ka.Fc = Fc;
+        BTD_TRY(btd::launch_couple_rhs(ka, s));
+        int rc = enqueue_solve_level(p, l + 1, R, Fc, Fc, sws, next, s);
+        if (rc != BTD_OK) return rc;
+        BTD_TRY(btd::launch_recover(ka, s));
+    }
+    return BTD_OK;
+}
+
+int ensure_configured() {
+    if (!g_configured) {
+        if (btd::configure_kernels() != hipSuccess) return BTD_ERR_LAUNCH;
+        g_configured = true;
+    }
+    return BTD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int btd_workspace_bytes(const btd_desc_t* desc, size_t* factor_ws, size_t* solve_ws) {
+    if (!valid_desc(desc)) return -1;
+    std::vector<LevelPlan> lv;
+    const size_t f = build_levels(desc, lv);
+    if (factor_ws) *factor_ws = f;
+    if (solve_ws) *solve_ws = solve_bytes_for(lv, desc->max_nrhs);
+    return BTD_OK;
+}
+
+int btd_factor(const btd_desc_t* desc, const double* A, const double* B, const double* C, void* factor_ws,
+               size_t factor_bytes, void* stream, btd_plan_t* out) {
+    if (!valid_desc(desc)) return -1;
+    if (!A) return -2;
+    if (!B) return -3;
+    if (!C) return -4;
+    if (!out) return -8;
+    *out = nullptr;
+    std::vector<LevelPlan> lv;
+    const size_t need = build_levels(desc, lv);
+    if (!factor_ws || ((uintptr_t)factor_ws % kAlign) != 0) return -5;
+    if (factor_bytes < need) return -6;
+    int rc = ensure_configured();
+    if (rc != BTD_OK) return rc;
+    btd_plan_s* p = new (std::nothrow) btd_plan_s;
+    if (!p) return BTD_ERR_LAUNCH;
+    p->desc = *desc;
+    p->desc.seps = nullptr;
+    p->levels = std::move(lv);
+    p->ws = (char*)factor_ws;
+    p->ws_bytes = factor_bytes;
+    p->A = A; p->B = B; p->C = C;
+    p->status = (unsigned long long*)factor_ws;
+    rc = enqueue_factor(p, (hipStream_t)stream);
+    if (rc != BTD_OK) { delete p; return rc; }
+    *out = p;
+    return BTD_OK;
+}
+
+int btd_solve(btd_plan_t plan, int32_t nrhs, const double* F, double* X, void* solve_ws, size_t solve_bytes,
+              void* stream) {
+    if (!plan) return -1;
+    if (nrhs < 1 || nrhs > plan->desc.max_nrhs) return -2;
+    if (!F) return -3;
+    if (!X) return -4;
+    const size_t need = solve_bytes_for(plan->levels, nrhs);
+    if (!solve_ws || ((uintptr_t)solve_ws % kAlign) != 0) return -5;
+    if (solve_bytes < need) return -6;
+    int rc = ensure_configured();
+    if (rc != BTD_OK) return rc;
+    return enqueue_solve_level(plan, 0, nrhs, F, X, (char*)solve_ws, 0, (hipStream_t)stream);
+}
+
+int btd_solve_batch(int32_t count, const btd_plan_t* plans, const int32_t* nrhs, const double* const* F,
+                    double* const* X, void* solve_ws, size_t solve_bytes, void* stream) {
+    if (count < 0 || (count > 0 && (!plans || !nrhs || !F || !X))) return -1;
+    for (int s = 0; s < count; ++s) {
+        if (!plans[s] || nrhs[s] < 1 || nrhs[s] > plans[s]->desc.max_nrhs || !F[s] || !X[s]) return -(1000 + s);
+    }
+    if (count > 0) {
+        size_t need = 0;
+        for (int s = 0; s < count; ++s) {
+            const size_t b = solve_bytes_for(plans[s]->levels, nrhs[s]);
+            if (b > need) need = b;
+        }
+        if (!solve_ws || ((uintptr_t)solve_ws % kAlign) != 0 || solve_bytes < need) return -6;
+    }
+    for (int s = 0; s < count; ++s) {
+        int rc = enqueue_solve_level(plans[s], 0, nrhs[s], F[s], X[s], (char*)solve_ws, 0, (hipStream_t)stream);
+        if (rc != BTD_OK) return rc;
+    }
+    return BTD_OK;
+}
+
+size_t btd_residual_work_bytes(int32_t N, int32_t M, int32_t R) {
+    (void)M;
+    if (N < 1 || R < 1) return 0;
+    return sizeof(double) * 2 * (size_t)N * R;
+}
+
+int btd_residual(int32_t N, int32_t M, int32_t R, const double* A, const double* B, const double* C,
+                 const double* X, const double* F, double* out, void* work, void* stream) {
+    if (N < 1 || M < 1 || R < 1 || N > 65535 * 1024) return -1;
+    if (!A) return -4;
+    if (!B) return -5;
+    if (!C) return -6;
+    if (!X) return -7;
+    if (!F) return -8;
+    if (!out) return -9;
+    if (!work) return -10;
+    BTD_TRY(btd::launch_residual(N, M, R, A, B, C, X, F, out, (double*)work, (hipStream_t)stream));
+    return BTD_OK;
+}
+
+int btd_get_info(btd_plan_t plan, int32_t* status, int32_t* block_row, int32_t* col) {
+    if (!plan) return -1;
+    unsigned long long key = ~0ULL;
+    if (hipMemcpy(&key, plan->status, sizeof(key), hipMemcpyDeviceToHost) != hipSuccess) return BTD_ERR_LAUNCH;
+    int st = BTD_OK, row = -1, c = -1;
+    if (key != ~0ULL) {
+        const int level = (int)(key >> 56);
+        row = (int)((key >> 32) & 0xffffff);
+        c = (int)((key >> 8) & 0xffffff);
+        st = (int)(key & 0xff);
+        // map a coupling-system row back to the separator row of the level above
+        for (int l = level; l > 0; --l) row = plan->levels[l - 1].sep[row + 1];
+    }
+    if (status) *status = st;
+    if (block_row) *block_row = row;
+    if (col) *col = c;
+    return BTD_OK;
+}
+
+int btd_plan_separators(btd_plan_t plan, int32_t* seps_out) {
+    if (!plan || !seps_out) return -1;
+    const LevelPlan& L = plan->levels[0];
+    for (int k = 0; k < L.P - 1; ++k) seps_out[k] = L.sep[k + 1];
+    return BTD_OK;
+}
+
+int btd_plan_level_parts(btd_plan_t plan, int32_t level) {
+    if (!plan || level < 0 || level >= (int)plan->levels.size()) return -1;
+    return plan->levels[level].P;
+}
+
+int btd_default_separators(int32_t N, int32_t P, int32_t* seps_out) {
+    if (N < 1 || P < 1 || (P > 1 && 2 * (int64_t)P - 1 > N) || (P > 1 && !seps_out)) return -1;
+    std::vector<int> sep;
+    equal_split(N, P, sep);
+    for (int k = 0; k < P - 1; ++k) seps_out[k] = sep[k + 1];
+    return BTD_OK;
+}
+
+int btd_default_coupling_parts(int32_t P, int32_t M, int32_t R) {
+    if (P < 1 || M < 1 || R < 1) return -1;
+    return coupling_parts(P, M, R);
+}
+
+void btd_plan_destroy(btd_plan_t plan) { delete plan; }
+
+const char* btd_status_string(int code) {
+    switch (code) {
+        case BTD_OK: return "ok";
+        case BTD_ERR_SINGULAR: return "exactly zero pivot in the LU of a diagonal block";
+        case BTD_ERR_NONFINITE: return "non-finite pivot in the LU of a diagonal block";
+        case BTD_ERR_LAUNCH: return "HIP launch or copy failed";
+        default: return code < 0 ? "invalid argument" : "unknown status";
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,86 @@
+"""Host-side checks of the C ABI (no GPU): the library loads, exports every
+symbol include/btd.h declares, validates arguments before touching the
+device, and its partition / recursion rules agree with the oracle's
+independent implementation."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import oracle
+from paper_1505_06864_amd import btd
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "btd.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(btd_\w+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = btd.lib()
+    declared = header_functions()
+    assert len(declared) >= 10
+    for name in declared:
+        assert hasattr(L, name), name
+    assert sorted(btd.EXPORTS) == declared
+
+
+def test_status_strings():
+    L = btd.lib()
+    for code in (0, 1, 2, 3, -1):
+        assert L.btd_status_string(code)
+
+
+@pytest.mark.parametrize("N,P,depth", [(1, 1, 0), (64, 4, 0), (2048, 512, 1), (4096, 64, 2)])
+def test_workspace_bytes_positive(N, P, depth):
+    f, s = btd.workspace_bytes(N, 16, P, depth, max_nrhs=4)
+    assert f > 0 and s > 0 and f % 256 == 0
+
+
+@pytest.mark.parametrize("kw", [dict(N=0, M=4), dict(N=8, M=0), dict(N=8, M=btd.BTD_MAX_M + 1),
+                                dict(N=8, M=4, P=5), dict(N=8, M=4, P=0), dict(N=8, M=4, depth=-1),
+                                dict(N=8, M=4, max_nrhs=0), dict(N=8, M=4, P=3, seps=[0, 4]),
+                                dict(N=8, M=4, P=3, seps=[3, 4]), dict(N=8, M=4, P=3, seps=[3, 7]),
+                                dict(N=8, M=4, P=3, seps=[5, 3])])
+def test_invalid_descriptions_rejected(kw):
+    with pytest.raises(btd.BtdError):
+        btd.workspace_bytes(**kw)
+
+
+def test_factor_rejects_bad_arguments_before_device_work():
+    L = btd.lib()
+    d, _k = btd.make_desc(8, 4, 2, 0, 1)
+    h = ctypes.c_void_p()
+    fake = ctypes.c_void_p(256)  # never dereferenced: every call below fails its host checks
+    assert L.btd_factor(None, fake, fake, fake, fake, 1 << 20, None, ctypes.byref(h)) == -1
+    assert L.btd_factor(ctypes.byref(d), None, fake, fake, fake, 1 << 20, None, ctypes.byref(h)) == -2
+    assert L.btd_factor(ctypes.byref(d), fake, None, fake, fake, 1 << 20, None, ctypes.byref(h)) == -3
+    assert L.btd_factor(ctypes.byref(d), fake, fake, None, fake, 1 << 20, None, ctypes.byref(h)) == -4
+    assert L.btd_factor(ctypes.byref(d), fake, fake, fake, None, 1 << 20, None, ctypes.byref(h)) == -5
+    assert L.btd_factor(ctypes.byref(d), fake, fake, fake, ctypes.c_void_p(258), 1 << 20, None,
+                        ctypes.byref(h)) == -5
+    assert L.btd_factor(ctypes.byref(d), fake, fake, fake, fake, 16, None, ctypes.byref(h)) == -6
+    assert L.btd_factor(ctypes.byref(d), fake, fake, fake, fake, 1 << 20, None, None) == -8
+    assert L.btd_solve(None, 1, fake, fake, fake, 1 << 20, None) == -1
+    assert L.btd_solve_batch(-1, None, None, None, None, None, 0, None) == -1
+    assert L.btd_solve_batch(0, None, None, None, None, None, 0, None) == 0
+    assert L.btd_residual(0, 4, 1, fake, fake, fake, fake, fake, fake, fake, None) == -1
+    assert L.btd_residual(4, 4, 1, fake, fake, fake, fake, fake, None, fake, None) == -9
+
+
+def test_partition_matches_oracle():
+    for N in range(1, 80):
+        for P in range(1, (N + 1) // 2 + 1):
+            assert btd.default_separators(N, P) == oracle.partition(N, P), (N, P)
+    for N, P in ((2048, 8), (2048, 512), (4096, 64), (4096, 241)):
+        assert btd.default_separators(N, P) == oracle.partition(N, P)
+
+
+def test_coupling_parts_match_oracle():
+    for P in range(1, 700):
+        for M, R in ((16, 1), (128, 4), (256, 64)):
+            assert btd.default_coupling_parts(P, M, R) == oracle.default_m(P, M, R), (P, M, R)
