@@ -181,6 +181,28 @@ int btd_plan_level_parts(btd_plan_t plan, int32_t level);
 int btd_default_separators(int32_t N, int32_t P, int32_t *seps_out);
 int btd_default_coupling_parts(int32_t P, int32_t M, int32_t R);
 
+/*
+ * Kernel timing for measurements: while a class is enabled, every launch of
+ * that kernel class (on the process's plans, any stream) is bracketed by a
+ * pair of HIP events recorded on the launch's stream.  btd_profile_read
+ * waits for the recorded events, returns the summed elapsed milliseconds and
+ * the number of launches since the last read, and releases the events.
+ * Classes: see BTD_KC_*.  btd_profile_enable(-1) disables.  Not
+ * thread-safe.  Returns 0, or -1 for an unknown class.
+ */
+#define BTD_KC_FWD_GEMM 0     /* D_i = A_i - B_i E_{i-1} and the left-spike product       */
+#define BTD_KC_GETRF 1        /* LU with partial pivoting of D_i                          */
+#define BTD_KC_GETRS_FACTOR 2 /* [E_i | Y_i] = D_i^{-1} [C_i | -B_i Y_{i-1}]               */
+#define BTD_KC_BWD_GEMM 3     /* backward sweep of the spikes                              */
+#define BTD_KC_COUPLE 4       /* coupling matrix assembly (Eq. e2311)                      */
+#define BTD_KC_RHS_SWEEP 5    /* per-chunk forward and backward sweep of the right-hand side */
+#define BTD_KC_COUPLE_RHS 6   /* coupling right-hand side (Eq. e2311)                      */
+#define BTD_KC_RECOVER 7      /* X = z - Z_L h^{k-1} - Z_R h^k (Eq. endSolution)           */
+#define BTD_KC_RESIDUAL 8     /* residual check                                            */
+#define BTD_KC_COUNT 9
+int btd_profile_enable(int32_t kernel_class);
+int btd_profile_read(double *total_ms, int64_t *launches);
+
 /* Releases the host handle.  The caller then owns factor_ws and A, B, C
  * again; enqueued work that uses them must have finished first. */
 void btd_plan_destroy(btd_plan_t plan);

@@ -23,7 +23,12 @@ BTD_MAX_M = 512
 # Every symbol include/btd.h declares.
 EXPORTS = ("btd_workspace_bytes", "btd_factor", "btd_solve", "btd_solve_batch", "btd_residual_work_bytes",
            "btd_residual", "btd_get_info", "btd_plan_separators", "btd_plan_level_parts",
-           "btd_default_separators", "btd_default_coupling_parts", "btd_plan_destroy", "btd_status_string")
+           "btd_default_separators", "btd_default_coupling_parts", "btd_profile_enable", "btd_profile_read",
+           "btd_plan_destroy", "btd_status_string")
+
+# Kernel classes of btd_profile_enable (BTD_KC_*).
+KERNEL_CLASSES = ("fwd_gemm", "getrf", "getrs_factor", "bwd_gemm", "couple", "rhs_sweep", "couple_rhs",
+                  "recover", "residual")
 
 
 class Desc(ctypes.Structure):
@@ -56,6 +61,8 @@ def lib():
         L.btd_plan_level_parts.argtypes = [vp, i32]
         L.btd_default_separators.argtypes = [i32, i32, ctypes.POINTER(i32)]
         L.btd_default_coupling_parts.argtypes = [i32, i32, i32]
+        L.btd_profile_enable.argtypes = [i32]
+        L.btd_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
         L.btd_plan_destroy.argtypes = [vp]
         L.btd_plan_destroy.restype = None
         L.btd_status_string.argtypes = [ctypes.c_int]
@@ -235,6 +242,23 @@ def solve_batch(plans, Fs, Xs=None, stream=None):
     torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
     del buf
     return Xs
+
+
+def profile_enable(kernel_class):
+    """Bracket every launch of one kernel class (name or BTD_KC_* index, None = off) with HIP events."""
+    idx = -1 if kernel_class is None else (KERNEL_CLASSES.index(kernel_class)
+                                           if isinstance(kernel_class, str) else int(kernel_class))
+    if lib().btd_profile_enable(idx) != BTD_OK:
+        raise ValueError(f"unknown kernel class {kernel_class}")
+
+
+def profile_read():
+    """(total milliseconds, launches) of the enabled class since the last read."""
+    ms, n = ctypes.c_double(), ctypes.c_int64()
+    rc = lib().btd_profile_read(ctypes.byref(ms), ctypes.byref(n))
+    if rc != BTD_OK:
+        raise BtdError(rc, "btd_profile_read")
+    return ms.value, n.value
 
 
 def residual(A, B, C, X, F, stream=None):

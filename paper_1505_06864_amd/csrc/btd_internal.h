@@ -19,7 +19,7 @@ namespace btd {
 struct Level {
     const double *A, *B, *C;  // [N][M][M]
     double* LU;               // [N][M][M]   LU factors of D_i (unit L below, U on/above the diagonal)
-    double* DI;               // [N][ceil(M/16)][2][16][16] inverses of the 16x16 diagonal blocks of L and U
+    double* DI;               // [N][ceil(M/32)][2][32][32] inverses of the 32x32 diagonal blocks of L and U
     double* W;                // [N][M][2M]  [E_i | Y_i]: E_i = D_i^{-1} C_i, Y = forward sweep of the left spike
     double* Z;                // [N][M][2M]  [Z_L | Z_R] spikes (P > 1)
     double *Hd, *Hb, *Hc;     // [P-1][M][M] coupling system (P > 1)
@@ -43,23 +43,22 @@ struct IntChunk {
     int v[CAP];
 };
 
-enum GemmMode { GM_FWD = 0, GM_BWD, GM_COUPLE, GM_RHS_FWD, GM_RHS_BWD, GM_COUPLE_RHS, GM_RECOVER };
+enum GemmMode { GM_FWD = 0, GM_BWD, GM_COUPLE, GM_COUPLE_RHS, GM_RECOVER };
 
 hipError_t launch_fwd_gemm(const KArgs& ka, hipStream_t s);
 hipError_t launch_bwd_gemm(const KArgs& ka, hipStream_t s);
 hipError_t launch_couple(const KArgs& ka, hipStream_t s);
-hipError_t launch_rhs_fwd(const KArgs& ka, hipStream_t s);
-hipError_t launch_rhs_bwd(const KArgs& ka, hipStream_t s);
 hipError_t launch_couple_rhs(const KArgs& ka, hipStream_t s);
 hipError_t launch_recover(const KArgs& ka, hipStream_t s);
 hipError_t launch_getrf(const KArgs& ka, hipStream_t s);
-hipError_t launch_getrs(const KArgs& ka, bool solve, hipStream_t s);
+hipError_t launch_diag_inv(const KArgs& ka, hipStream_t s);
+hipError_t launch_getrs(const KArgs& ka, hipStream_t s);
+hipError_t launch_chunk_solve(const KArgs& ka, hipStream_t s);
 hipError_t launch_init_status(unsigned long long* st, hipStream_t s);
 hipError_t launch_write_ints(int* dst, const int* host_vals, int count, hipStream_t s);
 hipError_t launch_residual(int N, int M, int R, const double* A, const double* B, const double* C,
                            const double* X, const double* F, double* out, double* work, hipStream_t s);
 size_t getrf_lds_bytes(int M);
-size_t getrs_lds_bytes(int M);
 hipError_t configure_kernels();
 
 }  // namespace btd

@@ -37,6 +37,99 @@ __device__ __forceinline__ v4d mfma4(double a, double b, v4d c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+
+// Cross-lane helpers.  DPP row permutations reduce within each 16-lane row
+// at VALU cost; readlane combines the four rows.
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double readlane_d(double v, int l) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                            __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+
+// DPP move that leaves the rows outside ROWMASK unchanged.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_upd(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(__double2loint(v), __double2loint(v), CTRL, ROWMASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(__double2hiint(v), __double2hiint(v), CTRL, ROWMASK, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Maximum over the 64 lanes (NaN inputs never win), returned as a uniform
+// value: row reduction by row permutations, then row_bcast15 / row_bcast31
+// carry the row maxima up to lane 63.
+__device__ __forceinline__ double wave_max(double v) {
+    v = fmax(v, dpp_mov<0xB1>(v));         // quad_perm [1,0,3,2]
+    v = fmax(v, dpp_mov<0x4E>(v));         // quad_perm [2,3,0,1]
+    v = fmax(v, dpp_mov<0x141>(v));        // row_half_mirror
+    v = fmax(v, dpp_mov<0x140>(v));        // row_mirror
+    v = fmax(v, dpp_upd<0x142, 0xa>(v));   // row_bcast15 into rows 1 and 3
+    v = fmax(v, dpp_upd<0x143, 0xc>(v));   // row_bcast31 into rows 2 and 3
+    return readlane_d(v, 63);
+}
+
+template <int CTRL>
+__device__ __forceinline__ int dpp_mov_i(int v) {
+    return __builtin_amdgcn_mov_dpp(v, CTRL, 0xf, 0xf, false);
+}
+
+// Minimum over the 64 lanes, returned to every lane.
+__device__ __forceinline__ int wave_min_int(int v) {
+    v = min(v, dpp_mov_i<0xB1>(v));
+    v = min(v, dpp_mov_i<0x4E>(v));
+    v = min(v, dpp_mov_i<0x141>(v));
+    v = min(v, dpp_mov_i<0x140>(v));
+    return min(min(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
+               min(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
+}
+
+// Workgroup copy of n elements with UNR loads in flight per thread before
+// the matching stores (a plain strided loop waits for every load).
+template <int UNR, class LD, class ST>
+__device__ __forceinline__ void copy_batched(int n, LD load, ST store) {
+    for (int base = threadIdx.x; base < n; base += 256 * UNR) {
+        double v[UNR];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            const int idx = base + u * 256;
+            v[u] = idx < n ? load(idx) : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            const int idx = base + u * 256;
+            if (idx < n) store(idx, v[u]);
+        }
+    }
+}
+
+#ifdef BTD_PHASE_TIMING
+__device__ unsigned long long g_phase[16];
+#define PHASE_MARK(var) const unsigned long long var = wall_clock64()
+#define PHASE_ADD(slot, a, b) if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) atomicAdd(&g_phase[slot], (b) - (a))
+#define PHASE_ADD_W1(slot, a, b) if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 64) atomicAdd(&g_phase[slot], (b) - (a))
+#else
+#define PHASE_MARK(var)
+#define PHASE_ADD(slot, a, b)
+#define PHASE_ADD_W1(slot, a, b)
+#endif
+
+// XCD-aware workgroup order.  Workgroups are dispatched round-robin over
+// the 8 XCDs (each with its own L2), so dispatch id d runs on XCD d mod 8.
+// The logical id returned here makes runs of consecutive logical ids share
+// one XCD; a kernel that gives the workgroups of one chunk consecutive
+// logical ids keeps that chunk's blocks in one L2.
+constexpr int NXCD = 8;
+__device__ __forceinline__ int xcd_logical_id(int d, int G) {
+    const int per = G / NXCD;
+    if (d >= per * NXCD) return d;
+    return (d % NXCD) * per + d / NXCD;
+}
+
 // Record a numerical failure; the smallest (level, row, col, code) key wins,
 // so the report is independent of scheduling.
 __device__ void report_status(unsigned long long* st, int level, int row, int col, int code) {
@@ -133,28 +226,6 @@ __device__ bool make_job(const KArgs& ka, int b, int part, Job& j) {
             j.Out = L.Hc + jj * MM; j.ldo = M;
             if (jj + 1 <= L.P - 2) { j.A1 = Cq; j.lda1 = M; j.B1 = L.Z + r * MM * 2 + M; j.ldb1 = M2; j.k1 = M; }
         }
-        return true;
-    } else if (MODE == GM_RHS_FWD) {
-        const int k = b, t = ka.step, R = ka.R;
-        const int r = chunk_first(L, k), e = chunk_last(L, k);
-        if (t > e - r) return false;
-        const int i = r + t;
-        const size_t MR = (size_t)M * R;
-        j.n = R;
-        j.Out = ka.X + i * MR; j.ldo = R;
-        j.Cin = ka.F + i * MR; j.ldc = R;
-        if (t > 0) { j.A1 = L.B + i * MM; j.lda1 = M; j.B1 = ka.X + (i - 1) * MR; j.ldb1 = R; j.k1 = M; }
-        return true;
-    } else if (MODE == GM_RHS_BWD) {
-        const int k = b, s = ka.step, R = ka.R;
-        const int r = chunk_first(L, k), e = chunk_last(L, k);
-        if (s < 1 || s > e - r) return false;
-        const int i = e - s;
-        const size_t MR = (size_t)M * R;
-        j.n = R;
-        j.Out = ka.X + i * MR; j.ldo = R;
-        j.Cin = ka.X + i * MR; j.ldc = R;
-        j.A1 = L.W + i * MM * 2; j.lda1 = M2; j.B1 = ka.X + (i + 1) * MR; j.ldb1 = R; j.k1 = M;
         return true;
     } else if (MODE == GM_COUPLE_RHS) {
         const int jj = b, q = L.sep[jj + 1], R = ka.R;
@@ -263,8 +334,10 @@ template <int MODE, int NPARTS>
 __global__ __launch_bounds__(256) void k_gemm(const KArgs ka, int tiles_m, int tiles_n) {
     __shared__ double As[KB * (TB + AP)];
     __shared__ double Bs[KB * (TB + BP)];
-    const int b = blockIdx.y;
-    int bx = blockIdx.x;
+    const int per_item = tiles_m * tiles_n * NPARTS;
+    const int lid = xcd_logical_id(blockIdx.x, gridDim.x);
+    const int b = lid / per_item;
+    int bx = lid % per_item;
     const int tn = bx % tiles_n; bx /= tiles_n;
     const int tm = bx % tiles_m; bx /= tiles_m;
     const int part = bx;
@@ -300,347 +373,888 @@ __global__ __launch_bounds__(256) void k_gemm(const KArgs ka, int tiles_m, int t
 
 // ------------------------------------------------------------------ LU
 //
-// One workgroup (256 threads) per diagonal block D_i: right-looking blocked
-// LU with partial pivoting (row interchanges; ties go to the lowest row).
-// Panel of NB columns held in LDS (column-major, pitch M+1); the pivot
-// search is a per-thread scan, a 64-lane shuffle argmax inside each wave and
-// a 4-entry combine across waves.  Row interchanges are applied to the
-// columns outside the panel and U12 = L11^{-1} A12 by one thread per column;
-// the trailing update A22 -= L21 U12 runs on FP64 MFMA in 32 x 32 wave tiles.
-// Epilogue: the permutation (row r of P D is row perm[r] of D) and the
-// inverses of the 16 x 16 diagonal blocks of L and U for the solves.
-constexpr int NB = 16;
+// One workgroup (8 waves, or 4 when the register panel needs the larger
+// per-wave register budget) per diagonal block D_i: blocked
+// right-looking LU with partial pivoting (row interchanges, ties to the
+// first maximum in the current row order), panels of NB columns, with
+// look-ahead:
+//   A(p)  wave 0 factors panel p held in its registers (lane l owns panel
+//         rows l, l+64, ...); the pivot search is a DPP/readlane reduction,
+//         rows stay in their lanes and only their positions change, and
+//         wave 0 finishes with inv(L11) of the panel.
+//   B(p)  all threads: the panel's interchanges are applied to the other
+//         columns as one gather, and U12 = inv(L11) A12 on MFMA.
+//   C(p)  A22 -= L21 U12 on MFMA: first the columns of panel p+1 (all
+//         waves), then wave 0 runs A(p+1) while the other waves update the
+//         rest.
+// The diagonal-block inverses for the triangular solves come from a
+// separate kernel.
+constexpr int DB = 32;                 // diagonal block of the triangular solves
+constexpr int DI_STRIDE = 2 * DB * DB; // doubles per diagonal block (L inverse, then U inverse)
 
-__global__ __launch_bounds__(256) void k_getrf(const KArgs ka) {
-    const Level& L = ka.L;
-    const int k = blockIdx.x, t = ka.step;
-    const int r = chunk_first(L, k), e = chunk_last(L, k);
-    if (t > e - r) return;
-    const int i = r + t;
-    const int M = L.M, PM = M + 1;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    double* a = L.LU + (size_t)i * M * M;
-    extern __shared__ double sm[];
-    double* pan = sm;                       // [NB][M+1]
-    double* us = pan + NB * PM;             // [NB][M]
-    double* redv = us + NB * M;             // [4]
-    int* redi = (int*)(redv + 4);           // [4]
-    int* swp = redi + 4;                    // [NB]
-    int* sperm = swp + NB;                  // [M]
+struct GetrfLds {
+    int PM, UM;
+    size_t pan, us, il, rowbuf, list, srcmap, naff, sperm, total;
+};
 
-    for (int rr = tid; rr < M; rr += 256) sperm[rr] = rr;
-    int fail_code = 0, fail_col = -1;
-    for (int j0 = 0; j0 < M; j0 += NB) {
-        const int nb = min(NB, M - j0), h = M - j0;
-        __syncthreads();
-        for (int idx = tid; idx < h * nb; idx += 256) {
-            const int rr = idx / nb, c = idx - rr * nb;
-            pan[c * PM + rr] = a[(size_t)(j0 + rr) * M + j0 + c];
+__host__ __device__ inline GetrfLds getrf_lds_layout(int M, int NB) {
+    GetrfLds l;
+    l.PM = M + 1;
+    l.UM = M;
+    size_t off = 0;
+    l.pan = off; off += sizeof(double) * 2 * (size_t)NB * l.PM;   // two panel buffers
+    l.us = off; off += sizeof(double) * (size_t)NB * l.UM;   // rows j0..j0+nb-1 of every column outside the panel
+    l.il = off; off += sizeof(double) * 16 * 16;
+    l.rowbuf = off; off += sizeof(double) * (2 * NB + 2);
+    l.list = off; off += sizeof(int) * 2 * NB;
+    l.srcmap = off; off += sizeof(int) * NB;
+    l.naff = off; off += sizeof(int) * 4;
+    l.sperm = off; off += sizeof(int) * (size_t)M;
+    l.total = off;
+    return l;
+}
+
+__device__ __forceinline__ void wave_lds_sync() { __asm__ volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
+// One column step JJ of the register-resident panel factorisation (wave 0),
+// expanded at compile time so every register index is static.  Rows never
+// move between lanes: pos[s] is the current position (0-based inside the
+// panel) of the row held in slot s, so a row interchange only swaps two
+// positions.  The pivot is the largest |value| among rows at positions >= JJ,
+// the lowest position on ties.  The pivot row is broadcast with readlane
+// (only the columns still needed), multipliers are scaled by the reciprocal
+// of the pivot, and the update is branch-free (inactive rows use a zero
+// multiplier).  The pivot value is recorded in rowbuf[JJ] (lane 0) for the
+// status check after the panel; rowbuf[NB..2NB) carries the pivot row.
+template <int RPL, int NB, int JJ>
+__device__ __forceinline__ void panel_column(double (&p)[RPL][NB], int (&pos)[RPL], int h, int lane,
+                                             double* rowbuf) {
+    double* piv_out = rowbuf;
+    if constexpr (JJ < NB) {
+        double bv = -1.0;
+#pragma unroll
+        for (int s = 0; s < RPL; ++s) {
+            const double v = fabs(p[s][JJ]);
+            bv = (pos[s] >= JJ && pos[s] < h && v > bv) ? v : bv;
         }
-        __syncthreads();
+        const double mx = wave_max(bv);
+        // lowest position holding the maximum
+        int cand = 0x7fffffff;
+#pragma unroll
+        for (int s = 0; s < RPL; ++s)
+            cand = (pos[s] >= JJ && pos[s] < h && fabs(p[s][JJ]) == mx && pos[s] < cand) ? pos[s] : cand;
+        const int ppos = wave_min_int(cand);
+        const bool found = ppos != 0x7fffffff;
+        // the winning lane publishes the rest of the pivot row through LDS
+#pragma unroll
+        for (int s = 0; s < RPL; ++s)
+            if (pos[s] == ppos) {
+#pragma unroll
+                for (int c = JJ; c < NB; ++c) rowbuf[NB + c] = p[s][c];
+            }
+        wave_lds_sync();
+        double prow[NB];
+#pragma unroll
+        for (int c = 0; c < NB; ++c) prow[c] = (c >= JJ && found) ? rowbuf[NB + c] : 0.0;
+        const int pj = found ? ppos : JJ;
+#pragma unroll
+        for (int s = 0; s < RPL; ++s) {
+            const int q = pos[s];
+            pos[s] = (q == JJ) ? pj : (q == pj ? JJ : q);
+        }
+        const double piv = found ? prow[JJ] : __longlong_as_double(0x7ff8000000000000ll);
+        if (lane == 0) piv_out[JJ] = piv;
+        const double rp = (piv != 0.0 && found) ? 1.0 / piv : 0.0;
+#pragma unroll
+        for (int s = 0; s < RPL; ++s) {
+            const bool act = pos[s] > JJ && pos[s] < h;
+            const double l = act ? p[s][JJ] * rp : 0.0;
+            p[s][JJ] = act ? l : p[s][JJ];
+#pragma unroll
+            for (int c = JJ + 1; c < NB; ++c) p[s][c] = fma(-l, prow[c], p[s][c]);
+        }
+        wave_lds_sync();
+        panel_column<RPL, NB, JJ + 1>(p, pos, h, lane, piv_out);
+    }
+}
+
+// A(p): wave 0 factors the panel at column j0 (nb columns, h rows) held in
+// registers, writes the factors to global memory and to the LDS panel buffer
+// `pan` (column-major, positions as rows), the map from the first nb
+// positions to their source rows, the list of rows displaced to positions
+// >= nb (at most one per column step, so at most nb), the running
+// permutation, and inv(L11) (16 x 16, zero-padded) into `il`.
+template <int RPL, int NB>
+__device__ __forceinline__ void lu_panel(double* a, int M, int j0, int PM, double* pan, double* il, double* rowbuf,
+                                         int* list, int* srcmap, int* naff_s, int* sperm, int lane, int& fail_code,
+                                         int& fail_col) {
+    const int nb = min(NB, M - j0), h = M - j0;
+    double p[RPL][NB];
+    int pos[RPL];
+#pragma unroll
+    for (int s = 0; s < RPL; ++s) {
+        const int r = s * 64 + lane;
+        pos[s] = r;
+#pragma unroll
+        for (int c = 0; c < NB; ++c)
+            p[s][c] = (r < h && c < nb) ? a[(size_t)(j0 + r) * M + j0 + c] : ((r == c) ? 1.0 : 0.0);
+    }
+    // rows past the end of the matrix are padded with the identity, so a
+    // ragged last panel needs no column guards
+    panel_column<RPL, NB, 0>(p, pos, max(h, NB), lane, rowbuf);
+    wave_lds_sync();
+    if (fail_code == 0) {
         for (int jj = 0; jj < nb; ++jj) {
-            double* colj = pan + jj * PM;
-            double bv = -1.0;
-            int bi = 0x7fffffff;
-            for (int rr = jj + tid; rr < h; rr += 256) {
-                const double v = fabs(colj[rr]);
-                if (v > bv) { bv = v; bi = rr; }
-            }
-#pragma unroll
-            for (int off = 32; off >= 1; off >>= 1) {
-                const double ov = __shfl_xor(bv, off);
-                const int oi = __shfl_xor(bi, off);
-                if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
-            }
-            if (lane == 0) { redv[w] = bv; redi[w] = bi; }
-            __syncthreads();
-            bv = redv[0]; bi = redi[0];
-#pragma unroll
-            for (int q = 1; q < 4; ++q)
-                if (redv[q] > bv || (redv[q] == bv && redi[q] < bi)) { bv = redv[q]; bi = redi[q]; }
-            const int p = (bi == 0x7fffffff) ? jj : bi;
-            if (p != jj)
-                for (int c = tid; c < nb; c += 256) {
-                    const double tmp = pan[c * PM + jj];
-                    pan[c * PM + jj] = pan[c * PM + p];
-                    pan[c * PM + p] = tmp;
-                }
-            if (tid == 0) {
-                swp[jj] = p;
-                if (p != jj) { const int tmp = sperm[j0 + jj]; sperm[j0 + jj] = sperm[j0 + p]; sperm[j0 + p] = tmp; }
-            }
-            __syncthreads();
-            const double piv = colj[jj];
-            if (fail_code == 0) {
-                if (bi == 0x7fffffff || !isfinite(piv)) { fail_code = BTD_ERR_NONFINITE_; fail_col = j0 + jj; }
-                else if (piv == 0.0) { fail_code = BTD_ERR_SINGULAR_; fail_col = j0 + jj; }
-            }
-            if (piv != 0.0) {
-                for (int rr = jj + 1 + tid; rr < h; rr += 256) {
-                    const double l = colj[rr] / piv;
-                    colj[rr] = l;
-                    for (int c = jj + 1; c < nb; ++c) pan[c * PM + rr] -= l * pan[c * PM + jj];
-                }
-            }
-            __syncthreads();
-        }
-        for (int idx = tid; idx < h * nb; idx += 256) {
-            const int rr = idx / nb, c = idx - rr * nb;
-            a[(size_t)(j0 + rr) * M + j0 + c] = pan[c * PM + rr];
-        }
-        // row interchanges outside the panel; U12 = L11^{-1} A12
-        for (int col = tid; col < M; col += 256) {
-            if (col >= j0 && col < j0 + nb) continue;
-            for (int jj = 0; jj < nb; ++jj) {
-                const int p = swp[jj];
-                if (p != jj) {
-                    const double tmp = a[(size_t)(j0 + jj) * M + col];
-                    a[(size_t)(j0 + jj) * M + col] = a[(size_t)(j0 + p) * M + col];
-                    a[(size_t)(j0 + p) * M + col] = tmp;
-                }
-            }
-            if (col >= j0 + nb) {
-                double u[NB];
-#pragma unroll
-                for (int jj = 0; jj < NB; ++jj) {
-                    if (jj < nb) {
-                        double s = a[(size_t)(j0 + jj) * M + col];
-#pragma unroll
-                        for (int c = 0; c < jj; ++c) s -= pan[c * PM + jj] * u[c];
-                        u[jj] = s;
-                        a[(size_t)(j0 + jj) * M + col] = s;
-                        us[jj * M + (col - j0 - nb)] = s;
-                    } else {
-                        u[jj] = 0.0;
-                    }
-                }
-            }
-        }
-        __syncthreads();
-        // trailing update A22 -= L21 U12 on MFMA
-        const int mt = h - nb;
-        if (mt > 0) {
-            const int t32 = (mt + 31) / 32;
-            double* a22 = a + (size_t)(j0 + nb) * M + j0 + nb;
-            for (int tile = w; tile < t32 * t32; tile += 4) {
-                const int tr = (tile / t32) * 32, tc = (tile % t32) * 32;
-                v4d acc[2][2];
-#pragma unroll
-                for (int x = 0; x < 2; ++x)
-#pragma unroll
-                    for (int y = 0; y < 2; ++y) {
-                        const int col = tc + 16 * y + (lane & 15);
-#pragma unroll
-                        for (int v = 0; v < 4; ++v) {
-                            const int row = tr + 16 * x + (lane >> 4) + 4 * v;
-                            acc[x][y][v] = (row < mt && col < mt) ? a22[(size_t)row * M + col] : 0.0;
-                        }
-                    }
-#pragma unroll
-                for (int kk = 0; kk < NB / 4; ++kk) {
-                    const int kr = kk * 4 + (lane >> 4);
-                    double av[2], bv2[2];
-#pragma unroll
-                    for (int x = 0; x < 2; ++x) {
-                        const int row = tr + 16 * x + (lane & 15);
-                        av[x] = (kr < nb && row < mt) ? -pan[kr * PM + nb + row] : 0.0;
-                    }
-#pragma unroll
-                    for (int y = 0; y < 2; ++y) {
-                        const int col = tc + 16 * y + (lane & 15);
-                        bv2[y] = (kr < nb && col < mt) ? us[kr * M + col] : 0.0;
-                    }
-#pragma unroll
-                    for (int x = 0; x < 2; ++x)
-#pragma unroll
-                        for (int y = 0; y < 2; ++y) acc[x][y] = mfma4(av[x], bv2[y], acc[x][y]);
-                }
-#pragma unroll
-                for (int x = 0; x < 2; ++x)
-#pragma unroll
-                    for (int y = 0; y < 2; ++y) {
-                        const int col = tc + 16 * y + (lane & 15);
-#pragma unroll
-                        for (int v = 0; v < 4; ++v) {
-                            const int row = tr + 16 * x + (lane >> 4) + 4 * v;
-                            if (row < mt && col < mt) a22[(size_t)row * M + col] = acc[x][y][v];
-                        }
-                    }
-            }
+            const double pv = rowbuf[jj];
+            if (!isfinite(pv)) { fail_code = BTD_ERR_NONFINITE_; fail_col = j0 + jj; break; }
+            if (pv == 0.0) { fail_code = BTD_ERR_SINGULAR_; fail_col = j0 + jj; break; }
         }
     }
-    __syncthreads();
-    int* perm = L.perm + (size_t)i * M;
-    for (int rr = tid; rr < M; rr += 256) perm[rr] = sperm[rr];
-    // inverses of the 16 x 16 diagonal blocks of L (unit lower) and U
-    const int nblk = (M + 15) / 16;
-    double* di = L.DI + (size_t)i * nblk * 512;
-    for (int idx = tid; idx < nblk * 16; idx += 256) {
-        const int bb = idx >> 4, jc = idx & 15, b0 = bb * 16, bs = min(16, M - b0);
+    int cnt = 0;
+#pragma unroll
+    for (int s = 0; s < RPL; ++s) {
+        const int r = s * 64 + lane, q = pos[s];
+        if (q < h) {
+#pragma unroll
+            for (int c = 0; c < NB; ++c)
+                if (c < nb) {
+                    a[(size_t)(j0 + q) * M + j0 + c] = p[s][c];
+                    pan[c * PM + q] = p[s][c];
+                }
+            if (q < nb) srcmap[q] = r;
+        }
+        const bool aff = (q < h) && (q >= nb) && (q != r);
+        const unsigned long long mask = __ballot(aff);
+        const int at = cnt + __popcll(mask & ((1ull << lane) - 1ull));
+        if (aff) { list[2 * at] = q; list[2 * at + 1] = r; }
+        cnt += __popcll(mask);
+    }
+    int tmp[RPL];
+#pragma unroll
+    for (int s = 0; s < RPL; ++s) {
+        const int r = s * 64 + lane;
+        tmp[s] = (r < h) ? sperm[j0 + r] : 0;
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int s = 0; s < RPL; ++s)
+        if (pos[s] < h) sperm[j0 + pos[s]] = tmp[s];
+    if (lane == 0) naff_s[0] = cnt;
+    // inv(L11), zero-padded to 16 x 16: lane jc < 16 computes column jc
+    if (lane < 16) {
+        const int jc = lane;
         double x[16];
 #pragma unroll
         for (int rr = 0; rr < 16; ++rr) {
             double s = (rr == jc) ? 1.0 : 0.0;
-            if (rr > jc && rr < bs) {
 #pragma unroll
-                for (int c = 0; c < rr; ++c)
-                    if (c >= jc) s -= a[(size_t)(b0 + rr) * M + b0 + c] * x[c];
-            }
-            x[rr] = s;
+            for (int c = 0; c < rr; ++c)
+                if (c < NB) s = fma(-pan[c * PM + rr], x[c], s);
+            x[rr] = (rr < nb && jc < nb) ? s : 0.0;
         }
 #pragma unroll
-        for (int rr = 0; rr < 16; ++rr) di[bb * 512 + rr * 16 + jc] = x[rr];
-        double y[16];
-#pragma unroll
-        for (int rr = 15; rr >= 0; --rr) {
-            double s;
-            if (rr >= bs) s = (rr == jc) ? 1.0 : 0.0;
-            else if (rr > jc) s = 0.0;
-            else {
-                s = (rr == jc) ? 1.0 : 0.0;
-#pragma unroll
-                for (int c = 15; c > rr; --c)
-                    if (c <= jc && c < bs) s -= a[(size_t)(b0 + rr) * M + b0 + c] * y[c];
-                s /= a[(size_t)(b0 + rr) * M + b0 + rr];
-            }
-            y[rr] = s;
-        }
-#pragma unroll
-        for (int rr = 0; rr < 16; ++rr) di[bb * 512 + 256 + rr * 16 + jc] = y[rr];
+        for (int rr = 0; rr < 16; ++rr) il[rr * 16 + jc] = x[rr];
     }
-    if (tid == 0 && fail_code != 0) {
-        // the failing row is reported as a row of the system this level solves
-        report_status(ka.status, L.level, i, fail_col, fail_code);
+}
+
+// A22 (mt x nt, row-major in global memory, leading dimension M) -= L21
+// (LDS panel rows nb.., column-major pitch PM) * U12 (LDS rows, pitch UM,
+// columns uc0..), one 32 x (16*CT) tile at (tr, tc): load, multiply, store.
+template <int CT>
+__device__ __forceinline__ void lu_tile_load(const double* a22, int M, int mt, int nt, int tr, int tc, int lane,
+                                             v4d (&acc)[2][CT]) {
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < CT; ++y) {
+            const int col = tc + 16 * y + (lane & 15);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = tr + 16 * x + (lane >> 4) + 4 * v;
+                acc[x][y][v] = (row < mt && col < nt) ? a22[(size_t)row * M + col] : 0.0;
+            }
+        }
+}
+
+template <int NB, int CT>
+__device__ __forceinline__ void lu_tile_mul(int mt, int nt, int tr, int tc, const double* pan, int PM, int nb,
+                                            const double* us, int UM, int uc0, int lane, v4d (&acc)[2][CT]) {
+#pragma unroll
+    for (int kk = 0; kk < NB / 4; ++kk) {
+        const int kr = kk * 4 + (lane >> 4);
+        double av[2], bw[CT];
+#pragma unroll
+        for (int x = 0; x < 2; ++x) {
+            const int row = tr + 16 * x + (lane & 15);
+            av[x] = (kr < nb && row < mt) ? -pan[kr * PM + nb + row] : 0.0;
+        }
+#pragma unroll
+        for (int y = 0; y < CT; ++y) {
+            const int col = tc + 16 * y + (lane & 15);
+            bw[y] = (kr < nb && col < nt) ? us[kr * UM + uc0 + col] : 0.0;
+        }
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+            for (int y = 0; y < CT; ++y) acc[x][y] = mfma4(av[x], bw[y], acc[x][y]);
+    }
+}
+
+template <int CT>
+__device__ __forceinline__ void lu_tile_store(double* a22, int M, int mt, int nt, int tr, int tc, int lane,
+                                              const v4d (&acc)[2][CT]) {
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < CT; ++y) {
+            const int col = tc + 16 * y + (lane & 15);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = tr + 16 * x + (lane >> 4) + 4 * v;
+                if (row < mt && col < nt) a22[(size_t)row * M + col] = acc[x][y][v];
+            }
+        }
+}
+
+template <int RPL, int NB, int LU_THREADS>
+__global__ __launch_bounds__(LU_THREADS) void k_getrf(const KArgs ka) {
+    const Level& L = ka.L;
+    const int k = blockIdx.x, t = ka.step;
+    const int r0 = chunk_first(L, k), e = chunk_last(L, k);
+    if (t > e - r0) return;
+    const int i = r0 + t;
+    const int M = L.M;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    constexpr int NW = LU_THREADS / 64;
+    double* a = L.LU + (size_t)i * M * M;
+    extern __shared__ double sm_raw[];
+    char* smc = (char*)sm_raw;
+    const GetrfLds lay = getrf_lds_layout(M, NB);
+    const int PM = lay.PM, UM = lay.UM;
+    double* pan0 = (double*)(smc + lay.pan);
+    double* ta = (double*)(smc + lay.us);
+    double* il = (double*)(smc + lay.il);
+    double* rowbuf = (double*)(smc + lay.rowbuf);
+    int* list = (int*)(smc + lay.list);
+    int* srcmap = (int*)(smc + lay.srcmap);
+    int* naff_s = (int*)(smc + lay.naff);
+    int* sperm = (int*)(smc + lay.sperm);
+
+    for (int rr = tid; rr < M; rr += LU_THREADS) sperm[rr] = rr;
+    int fail_code = 0, fail_col = -1;
+    __syncthreads();
+    PHASE_MARK(t_start);
+    const int npan = (M + NB - 1) / NB;
+    // iteration pidx: B and C of panel pidx, overlapped with A of panel pidx+1
+    for (int pidx = -1; pidx < npan; ++pidx) {
+        const int j0 = pidx * NB, nb = min(NB, M - j0), h = M - j0;
+        double* pan = pan0 + (size_t)(pidx & 1) * NB * PM;
+        const int nt = M - j0 - nb, mt = h - nb;
+        const int nb2 = min(NB, nt);
+        double* us = ta + (pidx >= 0 ? j0 + nb : 0);  // U12: rows of ta right of the panel
+        if (pidx >= 0) {
+            PHASE_MARK(t_b0);
+            // ---------------- B: interchanges outside the panel.  Rows j0..j0+nb-1 of
+            // every other column go through LDS (ta, pitch M); displaced rows are
+            // copied after all their sources are read; the L part (left columns)
+            // is written back, the right part stays in ta for U12.
+            const int naff = naff_s[0];
+            for (int c2 = tid; c2 < M - nb; c2 += LU_THREADS) {
+                const int col = c2 < j0 ? c2 : c2 + nb;
+                double top[NB];
+#pragma unroll
+                for (int jj = 0; jj < NB; ++jj) top[jj] = jj < nb ? a[(size_t)(j0 + srcmap[jj]) * M + col] : 0.0;
+#pragma unroll
+                for (int jj = 0; jj < NB; ++jj)
+                    if (jj < nb) ta[jj * M + col] = top[jj];
+                if (naff > 0) {
+                    double v[NB];
+#pragma unroll
+                    for (int q = 0; q < NB; ++q)
+                        if (q < naff) v[q] = a[(size_t)(j0 + list[2 * q + 1]) * M + col];
+#pragma unroll
+                    for (int q = 0; q < NB; ++q)
+                        if (q < naff) a[(size_t)(j0 + list[2 * q]) * M + col] = v[q];
+                }
+                if (col < j0) {
+#pragma unroll
+                    for (int jj = 0; jj < NB; ++jj)
+                        if (jj < nb) a[(size_t)(j0 + jj) * M + col] = ta[jj * M + col];
+                }
+            }
+            __syncthreads();
+            // U12 = inv(L11) A12 on MFMA, in place in us, and to global memory
+            for (int tcol = w * 16; tcol < nt; tcol += NW * 16) {
+                v4d acc = {0.0, 0.0, 0.0, 0.0};
+                const int col = tcol + (lane & 15);
+#pragma unroll
+                for (int kk = 0; kk < NB / 4; ++kk) {
+                    const int kr = kk * 4 + (lane >> 4);
+                    const double bw = col < nt ? us[kr * UM + col] : 0.0;
+                    acc = mfma4(il[(lane & 15) * 16 + kr], bw, acc);
+                }
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = (lane >> 4) + 4 * v;
+                    if (row < nb && col < nt) {
+                        us[row * UM + col] = acc[v];
+                        a[(size_t)(j0 + row) * M + j0 + nb + col] = acc[v];
+                    }
+                }
+            }
+            __syncthreads();
+            PHASE_MARK(t_c0);
+            PHASE_ADD(1, t_b0, t_c0);
+            // ---------------- C (first part): the columns of panel pidx+1, all waves
+            if (mt > 0) {
+                double* a22 = a + (size_t)(j0 + nb) * M + j0 + nb;
+                for (int tr = w * 32; tr < mt; tr += NW * 32) {
+                    v4d acc[2][1];
+                    lu_tile_load<1>(a22, M, mt, nb2, tr, 0, lane, acc);
+                    lu_tile_mul<NB, 1>(mt, nb2, tr, 0, pan, PM, nb, us, UM, 0, lane, acc);
+                    lu_tile_store<1>(a22, M, mt, nb2, tr, 0, lane, acc);
+                }
+            }
+            __syncthreads();
+        }
+        if (pidx + 1 >= npan) break;
+        PHASE_MARK(t_a0);
+        if (w == 0) {
+            // ---------------- A: panel pidx+1
+            double* pan_next = pan0 + (size_t)((pidx + 1) & 1) * NB * PM;
+            lu_panel<RPL, NB>(a, M, (pidx + 1) * NB, PM, pan_next, il, rowbuf, list, srcmap, naff_s, sperm, lane,
+                              fail_code, fail_col);
+            PHASE_MARK(t_a1);
+            PHASE_ADD(0, t_a0, t_a1);
+        } else if (pidx >= 0 && mt > 0) {
+            // ---------------- C (rest) of panel pidx: 32 x 32 tiles over waves 1..NW-1,
+            // the next tile's A22 loaded before the current one is multiplied
+            double* a22r = a + (size_t)(j0 + nb) * M + j0 + nb + nb2;
+            const int ntr = nt - nb2;
+            const int t32r = (mt + 31) / 32, t32c = (ntr + 31) / 32, ntiles = t32r * t32c;
+            v4d cur[2][2], nxt[2][2];
+            int tile = w - 1;
+            if (tile < ntiles) lu_tile_load<2>(a22r, M, mt, ntr, (tile / t32c) * 32, (tile % t32c) * 32, lane, cur);
+            while (tile < ntiles) {
+                const int tnext = tile + NW - 1;
+                if (tnext < ntiles)
+                    lu_tile_load<2>(a22r, M, mt, ntr, (tnext / t32c) * 32, (tnext % t32c) * 32, lane, nxt);
+                const int tr = (tile / t32c) * 32, tc = (tile % t32c) * 32;
+                lu_tile_mul<NB, 2>(mt, ntr, tr, tc, pan, PM, nb, us, UM, nb2, lane, cur);
+                lu_tile_store<2>(a22r, M, mt, ntr, tr, tc, lane, cur);
+#pragma unroll
+                for (int x = 0; x < 2; ++x)
+#pragma unroll
+                    for (int y = 0; y < 2; ++y) cur[x][y] = nxt[x][y];
+                tile = tnext;
+            }
+        }
+        __syncthreads();
+    }
+    PHASE_MARK(t_end);
+    PHASE_ADD(2, t_start, t_end);
+    int* perm = L.perm + (size_t)i * M;
+    for (int rr = tid; rr < M; rr += LU_THREADS) perm[rr] = sperm[rr];
+    if (lane == 0 && w == 0 && fail_code != 0) report_status(ka.status, L.level, i, fail_col, fail_code);
+}
+
+// Preparation of the factors of every D_i factored at this step for the
+// blocked triangular solves, one 256-thread workgroup per (32-column block
+// b, chunk):
+//   * the inverses of the diagonal blocks inv(L_bb) (unit lower) and
+//     inv(U_bb), padded with the identity past the end of the matrix, into DI;
+//   * the off-diagonal blocks of block column b scaled in place by them:
+//     L_{b',b} := L_{b',b} inv(L_bb) below the diagonal block and
+//     U_{b',b} := U_{b',b} inv(U_bb) above it (MFMA).
+// With the scaled blocks a sweep updates the other rows with the block
+// before its diagonal solve, so no diagonal product sits on the sweep's
+// sequential chain: for L y = r, w_b = r_b - sum_{b'<b} Lt_{b,b'} w_{b'} and
+// y_b = inv(L_bb) w_b; likewise for U.
+__global__ __launch_bounds__(256) void k_diag_prep(const KArgs ka) {
+    const Level& L = ka.L;
+    const int k = blockIdx.y, t = ka.step, M = L.M;
+    const int r0 = chunk_first(L, k), e = chunk_last(L, k);
+    if (t > e - r0) return;
+    const int i = r0 + t;
+    const int bb = blockIdx.x, b0 = bb * DB, bs = min(DB, M - b0);
+    const int nblk = (M + DB - 1) / DB;
+    double* a = L.LU + (size_t)i * M * M;
+    __shared__ double blk[DB * (DB + 1)];
+    __shared__ double inv[2][DB * (DB + 1)];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    for (int idx = tid; idx < DB * DB; idx += 256) {
+        const int rr = idx / DB, cc = idx % DB;
+        blk[rr * (DB + 1) + cc] = (rr < bs && cc < bs) ? a[(size_t)(b0 + rr) * M + b0 + cc] : 0.0;
+    }
+    __syncthreads();
+    if (tid < 2 * DB) {
+        const int which = tid / DB, jc = tid % DB;
+        double x[DB];
+        if (which == 0) {
+#pragma unroll
+            for (int rr = 0; rr < DB; ++rr) {
+                double s = (rr == jc) ? 1.0 : 0.0;
+#pragma unroll
+                for (int c = 0; c < rr; ++c) s = fma(-blk[rr * (DB + 1) + c], x[c], s);
+                x[rr] = (rr < bs || rr == jc) ? s : 0.0;
+            }
+        } else {
+#pragma unroll
+            for (int rr = DB - 1; rr >= 0; --rr) {
+                double s = (rr == jc) ? 1.0 : 0.0;
+#pragma unroll
+                for (int c = DB - 1; c > rr; --c) s = fma(-blk[rr * (DB + 1) + c], x[c], s);
+                x[rr] = rr < bs ? s / blk[rr * (DB + 1) + rr] : ((rr == jc) ? 1.0 : 0.0);
+            }
+        }
+        double* di = L.DI + (size_t)i * nblk * DI_STRIDE + (size_t)bb * DI_STRIDE + (which ? DB * DB : 0);
+#pragma unroll
+        for (int rr = 0; rr < DB; ++rr) {
+            di[rr * DB + jc] = x[rr];
+            inv[which][rr * (DB + 1) + jc] = x[rr];
+        }
+    }
+    __syncthreads();
+    // scale the off-diagonal blocks of this block column: 16-row strips, one wave each
+    for (int st = w; st < 2 * nblk; st += 4) {
+        if (st / 2 == bb) continue;
+        const int which = (st / 2 > bb) ? 0 : 1;
+        const int row0 = st * 16;
+        const int grow = row0 + (lane & 15);
+        double av[DB / 4];
+#pragma unroll
+        for (int kk = 0; kk < DB / 4; ++kk) {
+            const int gk = b0 + kk * 4 + (lane >> 4);
+            av[kk] = (grow < M && gk < M) ? a[(size_t)grow * M + gk] : 0.0;
+        }
+        v4d acc[2];
+#pragma unroll
+        for (int tc = 0; tc < 2; ++tc) {
+            acc[tc] = (v4d){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int kk = 0; kk < DB / 4; ++kk)
+                acc[tc] = mfma4(av[kk], inv[which][(kk * 4 + (lane >> 4)) * (DB + 1) + tc * 16 + (lane & 15)], acc[tc]);
+        }
+#pragma unroll
+        for (int tc = 0; tc < 2; ++tc) {
+            const int gc = b0 + tc * 16 + (lane & 15);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = row0 + (lane >> 4) + 4 * v;
+                if (row < M && gc < M) a[(size_t)row * M + gc] = acc[tc][v];
+            }
+        }
     }
 }
 
 // ------------------------------------------------------------------ triangular solves
 //
-// In place on an M x ncols right-hand side (row-major, leading dimension
-// ld): X := U^{-1} L^{-1} (P X), one slab of SW columns per workgroup held
-// in LDS.  Both sweeps go by 16-row blocks: X_b := inv(T_bb) X_b with the
-// inverted diagonal block, then the remaining rows are updated with the
-// off-diagonal panel on MFMA.  Column validity is decided per column, so a
-// slab can straddle the E and Y halves of W.
-template <int SW>
-__device__ void getrs_slab(const double* __restrict__ lu, const double* __restrict__ di,
-                           const int* __restrict__ perm, double* X, int ld, int M, int c0, int ncols, int valid_lo,
-                           int valid_hi, int valid2_lo, int valid2_hi, double* xs) {
-    constexpr int PX = SW + 2;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int nblk = (M + 15) / 16, Mp = nblk * 16;
-    auto valid = [&](int col) {
-        return col < ncols && ((col >= valid_lo && col < valid_hi) || (col >= valid2_lo && col < valid2_hi));
-    };
-    for (int idx = tid; idx < Mp * SW; idx += 256) {
-        const int rr = idx / SW, c = idx - rr * SW, col = c0 + c;
-        xs[rr * PX + c] = (rr < M && valid(col)) ? X[(size_t)perm[rr] * ld + col] : 0.0;
-    }
-    __syncthreads();
-    constexpr int NSUB = SW / 16;
-    // forward: unit lower
-    for (int bb = 0; bb < nblk; ++bb) {
-        const int b0 = bb * 16;
-        // X_b := invL_b X_b   (waves 0..NSUB-1, one 16-column subtile each)
-        if (w < NSUB) {
-            v4d acc = {0.0, 0.0, 0.0, 0.0};
-            const double* il = di + bb * 512;
+// In place on the M x 2M right-hand side W_i = [C_i | -B_i Y_{i-1}]
+// (row-major): X := U^{-1} L^{-1} (P X), one slab of SW columns per
+// 256-thread workgroup, with the scaled off-diagonal blocks prepared by
+// k_diag_prep.  The slab lives in MFMA accumulator registers: row block b
+// (32 rows) belongs to wave b mod 4.  Each sweep step publishes the current
+// (not yet diagonally solved) block b through a double-buffered LDS tile;
+// after one barrier every wave subtracts Lt_{b',b} X_b (forward, b' > b) or
+// Ut_{b',b} X_b (backward, b' < b) from its own blocks, with the operands of
+// the next step already in flight.  After each sweep every wave applies the
+// diagonal inverses to its own blocks.  Column validity is decided per
+// column, so a slab can straddle the E and Y halves of W.
+// The contraction index of the 32-wide block products is permuted so that
+// lane group g = lane >> 4 takes k = 8 g + kk at MFMA step kk: each lane's
+// eight operands of a row are then contiguous (two 32-byte loads) and the
+// LDS operand of step kk is row 8 g + kk.
+template <int SW, int BPW>
+__device__ __forceinline__ void trsm_load_ops(const double* __restrict__ lu, int M, int nblk, int dir, int b, int w,
+                                              int lane, double (&ops)[BPW][2][DB / 4]) {
+    const int g = lane >> 4;
 #pragma unroll
-            for (int kk = 0; kk < 4; ++kk) {
-                const int kr = kk * 4 + (lane >> 4);
-                acc = mfma4(il[(lane & 15) * 16 + kr], xs[(b0 + kr) * PX + w * 16 + (lane & 15)], acc);
+    for (int jb = 0; jb < BPW; ++jb) {
+        const int bp = w + 4 * jb;
+        const bool need = bp < nblk && (dir == 0 ? bp > b : bp < b);
+#pragma unroll
+        for (int tr = 0; tr < 2; ++tr) {
+            const int grow = bp * DB + tr * 16 + (lane & 15);
+            const int gk0 = b * DB + g * 8;
+            if (need && grow < M && gk0 + 7 < M && (M & 3) == 0) {  // 32-byte aligned rows
+                const double4* src = (const double4*)(lu + (size_t)grow * M + gk0);
+                const double4 v0 = src[0], v1 = src[1];
+                ops[jb][tr][0] = -v0.x; ops[jb][tr][1] = -v0.y; ops[jb][tr][2] = -v0.z; ops[jb][tr][3] = -v0.w;
+                ops[jb][tr][4] = -v1.x; ops[jb][tr][5] = -v1.y; ops[jb][tr][6] = -v1.z; ops[jb][tr][7] = -v1.w;
+            } else {
+#pragma unroll
+                for (int kk = 0; kk < DB / 4; ++kk) {
+                    const int gk = gk0 + kk;
+                    ops[jb][tr][kk] = (need && grow < M && gk < M) ? -lu[(size_t)grow * M + gk] : 0.0;
+                }
             }
-            __builtin_amdgcn_s_waitcnt(0);
-            __builtin_amdgcn_wave_barrier();
-#pragma unroll
-            for (int v = 0; v < 4; ++v) xs[(b0 + (lane >> 4) + 4 * v) * PX + w * 16 + (lane & 15)] = acc[v];
         }
-        __syncthreads();
-        const int nstrip = nblk - bb - 1;
-        for (int job = w; job < nstrip * NSUB; job += 4) {
-            const int st = job / NSUB, sub = job - st * NSUB;
-            const int row0 = b0 + 16 + st * 16, col = sub * 16 + (lane & 15);
-            v4d acc;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) acc[v] = xs[(row0 + (lane >> 4) + 4 * v) * PX + col];
-#pragma unroll
-            for (int kk = 0; kk < 4; ++kk) {
-                const int kr = kk * 4 + (lane >> 4);
-                const int grow = row0 + (lane & 15), gk = b0 + kr;
-                const double av = (grow < M && gk < M) ? -lu[(size_t)grow * M + gk] : 0.0;
-                acc = mfma4(av, xs[(b0 + kr) * PX + col], acc);
-            }
-#pragma unroll
-            for (int v = 0; v < 4; ++v) xs[(row0 + (lane >> 4) + 4 * v) * PX + col] = acc[v];
-        }
-        __syncthreads();
-    }
-    // backward: upper
-    for (int bb = nblk - 1; bb >= 0; --bb) {
-        const int b0 = bb * 16;
-        if (w < NSUB) {
-            v4d acc = {0.0, 0.0, 0.0, 0.0};
-            const double* iu = di + bb * 512 + 256;
-#pragma unroll
-            for (int kk = 0; kk < 4; ++kk) {
-                const int kr = kk * 4 + (lane >> 4);
-                acc = mfma4(iu[(lane & 15) * 16 + kr], xs[(b0 + kr) * PX + w * 16 + (lane & 15)], acc);
-            }
-            __builtin_amdgcn_s_waitcnt(0);
-            __builtin_amdgcn_wave_barrier();
-#pragma unroll
-            for (int v = 0; v < 4; ++v) xs[(b0 + (lane >> 4) + 4 * v) * PX + w * 16 + (lane & 15)] = acc[v];
-        }
-        __syncthreads();
-        for (int job = w; job < bb * NSUB; job += 4) {
-            const int st = job / NSUB, sub = job - st * NSUB;
-            const int row0 = st * 16, col = sub * 16 + (lane & 15);
-            v4d acc;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) acc[v] = xs[(row0 + (lane >> 4) + 4 * v) * PX + col];
-#pragma unroll
-            for (int kk = 0; kk < 4; ++kk) {
-                const int kr = kk * 4 + (lane >> 4);
-                const int grow = row0 + (lane & 15), gk = b0 + kr;
-                const double av = (gk < M) ? -lu[(size_t)grow * M + gk] : 0.0;
-                acc = mfma4(av, xs[(b0 + kr) * PX + col], acc);
-            }
-#pragma unroll
-            for (int v = 0; v < 4; ++v) xs[(row0 + (lane >> 4) + 4 * v) * PX + col] = acc[v];
-        }
-        __syncthreads();
-    }
-    for (int idx = tid; idx < M * SW; idx += 256) {
-        const int rr = idx / SW, c = idx - rr * SW, col = c0 + c;
-        if (valid(col)) X[(size_t)rr * ld + col] = xs[rr * PX + c];
     }
 }
 
-// Factor mode: RHS = W_i = [C_i | -B_i Y_{i-1}] of chunk blockIdx.y at step t.
-// Solve mode: RHS = X_i (R columns).
-template <int SW, bool SOLVE>
+// X_jb := inv(T_bb) X_jb for all of this wave's blocks (dir 0: L, 1: U),
+// through the wave's own LDS tile.
+template <int SW, int BPW>
+__device__ __forceinline__ void trsm_diag_own(const double* __restrict__ di, int nblk, int dir, int w, int lane,
+                                              v4d (&x)[BPW][2][SW / 16], double* own) {
+    constexpr int NSUB = SW / 16, PX = SW + 2;
+#pragma unroll
+    for (int jb = 0; jb < BPW; ++jb) {
+        const int b = w + 4 * jb;
+        if (b < nblk) {
+            const double* inv = di + (size_t)b * DI_STRIDE + (dir == 0 ? 0 : DB * DB);
+            double ia[2][DB / 4];
+#pragma unroll
+            for (int tr = 0; tr < 2; ++tr)
+#pragma unroll
+                for (int kk = 0; kk < DB / 4; ++kk) ia[tr][kk] = inv[(tr * 16 + (lane & 15)) * DB + kk * 4 + (lane >> 4)];
+#pragma unroll
+            for (int tr = 0; tr < 2; ++tr)
+#pragma unroll
+                for (int tc = 0; tc < NSUB; ++tc)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) own[(tr * 16 + (lane >> 4) + 4 * v) * PX + tc * 16 + (lane & 15)] = x[jb][tr][tc][v];
+            wave_lds_sync();
+#pragma unroll
+            for (int tr = 0; tr < 2; ++tr)
+#pragma unroll
+                for (int tc = 0; tc < NSUB; ++tc) {
+                    v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                    for (int kk = 0; kk < DB / 4; ++kk)
+                        acc = mfma4(ia[tr][kk], own[(kk * 4 + (lane >> 4)) * PX + tc * 16 + (lane & 15)], acc);
+                    x[jb][tr][tc] = acc;
+                }
+            wave_lds_sync();
+        }
+    }
+}
+
+template <int SW, int BPW>
+__device__ void getrs_slab(const double* __restrict__ lu, const double* __restrict__ di,
+                           const int* __restrict__ perm, double* X, int ld, int M, int c0, int ncols, int valid_lo,
+                           int valid_hi, int valid2_lo, int valid2_hi, double* xb /* 2 x [DB][SW+2] */,
+                           double* ownb /* 4 x [DB][SW+2] */) {
+    constexpr int NSUB = SW / 16;
+    constexpr int PX = SW + 2;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int nblk = (M + DB - 1) / DB;
+    double* own = ownb + (size_t)w * DB * PX;
+    PHASE_MARK(g_t0);
+    auto valid = [&](int col) {
+        return col < ncols && ((col >= valid_lo && col < valid_hi) || (col >= valid2_lo && col < valid2_hi));
+    };
+    // the slab, permuted, into accumulator registers
+    v4d x[BPW][2][NSUB];
+#pragma unroll
+    for (int jb = 0; jb < BPW; ++jb)
+#pragma unroll
+        for (int tr = 0; tr < 2; ++tr)
+#pragma unroll
+            for (int tc = 0; tc < NSUB; ++tc) {
+                const int col = c0 + tc * 16 + (lane & 15);
+                const bool cv = valid(col);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = (w + 4 * jb) * DB + tr * 16 + (lane >> 4) + 4 * v;
+                    x[jb][tr][tc][v] = (row < M && cv) ? X[(size_t)perm[row] * ld + col] : 0.0;
+                }
+            }
+    double ops[BPW][2][DB / 4];
+    trsm_load_ops<SW, BPW>(lu, M, nblk, 0, 0, w, lane, ops);
+    int buf = 0;
+    PHASE_MARK(g_t1);
+    PHASE_ADD(5, g_t0, g_t1);
+    for (int dir = 0; dir < 2; ++dir) {
+        for (int step = 0; step < nblk; ++step) {
+            const int b = dir == 0 ? step : nblk - 1 - step;
+            double* xt = xb + (size_t)buf * DB * PX;
+            if (w == (b & 3)) {
+#pragma unroll
+                for (int jb = 0; jb < BPW; ++jb)
+                    if (jb == (b >> 2)) {
+#pragma unroll
+                        for (int tr = 0; tr < 2; ++tr)
+#pragma unroll
+                            for (int tc = 0; tc < NSUB; ++tc)
+#pragma unroll
+                                for (int v = 0; v < 4; ++v)
+                                    xt[(tr * 16 + (lane >> 4) + 4 * v) * PX + tc * 16 + (lane & 15)] = x[jb][tr][tc][v];
+                    }
+            }
+            PHASE_MARK(g_b0);
+            __syncthreads();
+            PHASE_MARK(g_b1);
+            PHASE_ADD(6, g_b0, g_b1);
+            PHASE_ADD_W1(12, g_b0, g_b1);
+            double cur[BPW][2][DB / 4];
+#pragma unroll
+            for (int jb = 0; jb < BPW; ++jb)
+#pragma unroll
+                for (int tr = 0; tr < 2; ++tr)
+#pragma unroll
+                    for (int kk = 0; kk < DB / 4; ++kk) cur[jb][tr][kk] = ops[jb][tr][kk];
+            if (step + 1 < nblk) trsm_load_ops<SW, BPW>(lu, M, nblk, dir, dir == 0 ? step + 1 : nblk - 2 - step, w, lane, ops);
+            else if (dir == 0) trsm_load_ops<SW, BPW>(lu, M, nblk, 1, nblk - 1, w, lane, ops);
+#pragma unroll
+            for (int jb = 0; jb < BPW; ++jb) {
+                const int bp = w + 4 * jb;
+                if (bp < nblk && (dir == 0 ? bp > b : bp < b)) {
+#pragma unroll
+                    for (int tr = 0; tr < 2; ++tr)
+#pragma unroll
+                        for (int tc = 0; tc < NSUB; ++tc)
+#pragma unroll
+                            for (int kk = 0; kk < DB / 4; ++kk)
+                                x[jb][tr][tc] = mfma4(cur[jb][tr][kk],
+                                                      xt[((lane >> 4) * 8 + kk) * PX + tc * 16 + (lane & 15)],
+                                                      x[jb][tr][tc]);
+                }
+            }
+            buf ^= 1;
+            PHASE_MARK(g_b2);
+            PHASE_ADD(7, g_b1, g_b2);
+            PHASE_ADD_W1(13, g_b1, g_b2);
+        }
+        // diagonal solves of this wave's blocks (off the sequential chain)
+        PHASE_MARK(g_d0);
+        trsm_diag_own<SW, BPW>(di, nblk, dir, w, lane, x, own);
+        PHASE_MARK(g_d1);
+        PHASE_ADD(10, g_d0, g_d1);
+    }
+#pragma unroll
+    for (int jb = 0; jb < BPW; ++jb)
+#pragma unroll
+        for (int tr = 0; tr < 2; ++tr)
+#pragma unroll
+            for (int tc = 0; tc < NSUB; ++tc) {
+                const int col = c0 + tc * 16 + (lane & 15);
+                const bool cv = valid(col);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = (w + 4 * jb) * DB + tr * 16 + (lane >> 4) + 4 * v;
+                    if (row < M && cv) X[(size_t)row * ld + col] = x[jb][tr][tc][v];
+                }
+            }
+    PHASE_MARK(g_t2);
+    PHASE_ADD(11, g_t1, g_t2);
+    PHASE_ADD(4, g_t0, g_t2);
+}
+
+// RHS = W_i = [C_i | -B_i Y_{i-1}] of chunk blockIdx.y at step t.
+template <int SW, int BPW>
 __global__ __launch_bounds__(256) void k_getrs(const KArgs ka) {
-    extern __shared__ double xs[];
+    __shared__ double xb[2 * DB * (SW + 2)];
+    __shared__ double ownb[4 * DB * (SW + 2)];
     const Level& L = ka.L;
-    const int k = blockIdx.y, t = ka.step, M = L.M;
+    const int M = L.M, nslab = (2 * M + SW - 1) / SW;
+    const int lid = xcd_logical_id(blockIdx.x, gridDim.x);
+    const int k = lid / nslab, t = ka.step;
     const int r = chunk_first(L, k), e = chunk_last(L, k);
     if (t > e - r) return;
     const int i = r + t;
-    const int c0 = blockIdx.x * SW;
-    const int nblk = (M + 15) / 16;
+    const int c0 = (lid % nslab) * SW;
+    const int nblk = (M + DB - 1) / DB;
     const double* lu = L.LU + (size_t)i * M * M;
-    const double* di = L.DI + (size_t)i * nblk * 512;
+    const double* di = L.DI + (size_t)i * nblk * DI_STRIDE;
     const int* perm = L.perm + (size_t)i * M;
-    if (SOLVE) {
-        if (c0 >= ka.R) return;
-        getrs_slab<SW>(lu, di, perm, ka.X + (size_t)i * M * ka.R, ka.R, M, c0, ka.R, 0, ka.R, 0, 0, xs);
-    } else {
-        const int e_lo = 0, e_hi = (i != L.N - 1) ? M : 0;
-        const int y_lo = M, y_hi = (k > 0) ? 2 * M : M;
-        const int c_end = c0 + SW;
-        const bool any = (c0 < e_hi && c_end > e_lo) || (c0 < y_hi && c_end > y_lo);
-        if (!any) return;
-        getrs_slab<SW>(lu, di, perm, L.W + (size_t)i * M * M * 2, 2 * M, M, c0, 2 * M, e_lo, e_hi, y_lo, y_hi, xs);
+    const int e_lo = 0, e_hi = (i != L.N - 1) ? M : 0;
+    const int y_lo = M, y_hi = (k > 0) ? 2 * M : M;
+    const int c_end = c0 + SW;
+    const bool any = (c0 < e_hi && c_end > e_lo) || (c0 < y_hi && c_end > y_lo);
+    if (!any) return;
+    getrs_slab<SW, BPW>(lu, di, perm, L.W + (size_t)i * M * M * 2, 2 * M, M, c0, 2 * M, e_lo, e_hi, y_lo, y_hi, xb,
+                        ownb);
+}
+
+// ------------------------------------------------------------------ right-hand-side sweeps
+//
+// One workgroup per (chunk, group of RB columns) runs the chunk's whole
+// right-hand-side sweep (the F part of Eq. e231 by the Thomas algorithm of
+// Sec. 3 with LU factors):
+//   forward   y_i = U_i^{-1} L_i^{-1} P_i (F_i - B_i y_{i-1})
+//   backward  z_i = y_i - E_i z_{i+1}   (z_last = y_last)
+// The working block (M x RB) lives in LDS; B_i and E_i stream through LDS in
+// 32-column panels read row-contiguously; the triangular solves go by 32-row
+// blocks with the inverted diagonal blocks and the off-diagonal panel read
+// straight from the LU factors.  The solution is written to X (rows of the
+// chunk), which may alias F.
+template <int RB, int KC>
+__device__ __forceinline__ void lds_gemv_sub(const double* __restrict__ Mat, int ld, int M, const double* v, double* t,
+                                             double* st) {
+    // t (M x RB, LDS) -= Mat (M x M, row-major, global) * v (M x RB, LDS); the
+    // next KC-column panel is loaded into registers while the current one is used
+    const int tid = threadIdx.x;
+    constexpr int SP = KC + 1;
+    constexpr int PER = (BTD_MAX_M * KC + 255) / 256 > 32 ? 32 : (BTD_MAX_M * KC + 255) / 256;
+    double nx[PER];
+    auto load_panel = [&](int kc) {
+        const int kw = min(KC, M - kc);
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int idx = tid + u * 256, rr = idx / KC, cc = idx - rr * KC;
+            nx[u] = (rr < M && cc < kw) ? Mat[(size_t)rr * ld + kc + cc] : 0.0;
+        }
+    };
+    load_panel(0);
+    for (int kc = 0; kc < M; kc += KC) {
+        const int kw = min(KC, M - kc);
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int idx = tid + u * 256, rr = idx / KC, cc = idx - rr * KC;
+            if (rr < M) st[rr * SP + cc] = nx[u];
+        }
+        __syncthreads();
+        if (kc + KC < M) load_panel(kc + KC);
+        for (int rr = tid; rr < M; rr += 256) {
+            double acc[RB];
+#pragma unroll
+            for (int c = 0; c < RB; ++c) acc[c] = 0.0;
+#pragma unroll 8
+            for (int cc = 0; cc < KC; ++cc) {
+                if (cc < kw) {
+                    const double m = st[rr * SP + cc];
+#pragma unroll
+                    for (int c = 0; c < RB; ++c) acc[c] += m * v[(kc + cc) * RB + c];
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < RB; ++c) t[rr * RB + c] -= acc[c];
+        }
+    }
+    __syncthreads();
+}
+
+template <int RB>
+__device__ __forceinline__ void lds_lu_solve(const double* __restrict__ lu, const double* __restrict__ di, int M,
+                                             double* t, double* t2) {
+    // t := U^{-1} L^{-1} t (rows already permuted) with the scaled
+    // off-diagonal blocks: each sweep step updates the other rows with the
+    // unsolved block (one barrier), then all diagonal blocks are solved at
+    // once.  t2 is scratch; the result ends in t.
+    const int tid = threadIdx.x;
+    const int nblk = (M + DB - 1) / DB;
+    for (int dir = 0; dir < 2; ++dir) {
+        for (int step = 0; step < nblk; ++step) {
+            const int bb = dir == 0 ? step : nblk - 1 - step;
+            const int b0 = bb * DB, bs = min(DB, M - b0);
+            const int lo = dir == 0 ? b0 + bs : 0, hi = dir == 0 ? M : b0;
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const int rr = lo + tid + q * 256;
+                if (rr < hi) {
+                    double seg[DB];
+#pragma unroll
+                    for (int j = 0; j < DB; ++j) seg[j] = j < bs ? lu[(size_t)rr * M + b0 + j] : 0.0;
+                    double acc[RB];
+#pragma unroll
+                    for (int c = 0; c < RB; ++c) acc[c] = 0.0;
+#pragma unroll
+                    for (int j = 0; j < DB; ++j) {
+                        if (j < bs) {
+#pragma unroll
+                            for (int c = 0; c < RB; ++c) acc[c] += seg[j] * t[(b0 + j) * RB + c];
+                        }
+                    }
+#pragma unroll
+                    for (int c = 0; c < RB; ++c) t[rr * RB + c] -= acc[c];
+                }
+            }
+            __syncthreads();
+        }
+        // all diagonal blocks at once: t2 = inv(T_bb) t_b
+        for (int rr = tid; rr < M; rr += 256) {
+            const int bb = rr / DB, b0 = bb * DB, bs = min(DB, M - b0);
+            const double* inv = di + (size_t)bb * DI_STRIDE + (dir == 0 ? 0 : DB * DB) + (size_t)(rr - b0) * DB;
+            double iv[DB];
+#pragma unroll
+            for (int j = 0; j < DB; ++j) iv[j] = inv[j];
+            double acc[RB];
+#pragma unroll
+            for (int c = 0; c < RB; ++c) acc[c] = 0.0;
+#pragma unroll
+            for (int j = 0; j < DB; ++j) {
+                if (j < bs) {
+#pragma unroll
+                    for (int c = 0; c < RB; ++c) acc[c] += iv[j] * t[(b0 + j) * RB + c];
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < RB; ++c) t2[rr * RB + c] = acc[c];
+        }
+        __syncthreads();
+        double* sw = t;
+        t = t2;
+        t2 = sw;
+    }
+}
+
+template <int RB, int KC>
+__global__ __launch_bounds__(256) void k_chunk_solve(const KArgs ka) {
+    const Level& L = ka.L;
+    const int k = blockIdx.x, c0 = blockIdx.y * RB, R = ka.R, M = L.M;
+    if (c0 >= R) return;
+    const int nc = min(RB, R - c0);
+    const int r0 = chunk_first(L, k), e = chunk_last(L, k);
+    const int nblk = (M + DB - 1) / DB;
+    const int tid = threadIdx.x;
+    extern __shared__ double sm[];
+    double* ya = sm;                       // [M][RB] previous row's block
+    double* tb = ya + (size_t)M * RB;      // [M][RB] current block
+    double* tp = tb + (size_t)M * RB;      // [M][RB] permutation buffer
+    double* tmp = tp + (size_t)M * RB;     // [DB][RB]
+    double* ib = tmp + DB * RB;            // [DB][DB] inverted diagonal block
+    double* st = ib + DB * DB;             // [M][KC+1] staging panel
+    const size_t MM = (size_t)M * M, MR = (size_t)M * R;
+    // forward sweep
+    for (int i = r0; i <= e; ++i) {
+        copy_batched<8>(
+            M * RB,
+            [&](int idx) {
+                const int rr = idx / RB, c = idx - rr * RB;
+                return c < nc ? ka.F[i * MR + (size_t)rr * R + c0 + c] : 0.0;
+            },
+            [&](int idx, double v) { tb[idx] = v; });
+        __syncthreads();
+        PHASE_MARK(g0);
+        if (i > r0) lds_gemv_sub<RB, KC>(L.B + i * MM, M, M, ya, tb, st);
+        PHASE_MARK(g1);
+        PHASE_ADD(8, g0, g1);
+        const int* perm = L.perm + (size_t)i * M;
+        for (int idx = tid; idx < M * RB; idx += 256) {
+            const int rr = idx / RB, c = idx - rr * RB;
+            tp[idx] = tb[perm[rr] * RB + c];
+        }
+        __syncthreads();
+        PHASE_MARK(l0);
+        lds_lu_solve<RB>(L.LU + i * MM, L.DI + (size_t)i * nblk * DI_STRIDE, M, tp, tb);
+        PHASE_MARK(l1);
+        PHASE_ADD(9, l0, l1);
+        for (int idx = tid; idx < M * RB; idx += 256) {
+            const int rr = idx / RB, c = idx - rr * RB;
+            ya[idx] = tp[idx];
+            if (c < nc) ka.X[i * MR + (size_t)rr * R + c0 + c] = tp[idx];
+        }
+        __syncthreads();
+    }
+    // backward sweep: ya holds z of the row below
+    for (int i = e - 1; i >= r0; --i) {
+        copy_batched<8>(
+            M * RB,
+            [&](int idx) {
+                const int rr = idx / RB, c = idx - rr * RB;
+                return c < nc ? ka.X[i * MR + (size_t)rr * R + c0 + c] : 0.0;
+            },
+            [&](int idx, double v) { tb[idx] = v; });
+        __syncthreads();
+        lds_gemv_sub<RB, KC>(L.W + i * MM * 2, 2 * M, M, ya, tb, st);
+        for (int idx = tid; idx < M * RB; idx += 256) {
+            const int rr = idx / RB, c = idx - rr * RB;
+            ya[idx] = tb[idx];
+            if (c < nc) ka.X[i * MR + (size_t)rr * R + c0 + c] = tb[idx];
+        }
+        __syncthreads();
     }
 }
 
@@ -723,7 +1337,7 @@ static inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 template <int MODE, int NPARTS>
 static hipError_t launch_gemm(const KArgs& ka, int batch, int m, int n, hipStream_t s) {
     const int tm = cdiv(m, TB), tn = cdiv(n, TB);
-    dim3 grid(tm * tn * NPARTS, batch);
+    dim3 grid(tm * tn * NPARTS * batch);
     hipLaunchKernelGGL((k_gemm<MODE, NPARTS>), grid, dim3(256), 0, s, ka, tm, tn);
     return hipGetLastError();
 }
@@ -731,40 +1345,77 @@ static hipError_t launch_gemm(const KArgs& ka, int batch, int m, int n, hipStrea
 hipError_t launch_fwd_gemm(const KArgs& ka, hipStream_t s) { return launch_gemm<GM_FWD, 2>(ka, ka.L.P, ka.L.M, ka.L.M, s); }
 hipError_t launch_bwd_gemm(const KArgs& ka, hipStream_t s) { return launch_gemm<GM_BWD, 2>(ka, ka.L.P, ka.L.M, ka.L.M, s); }
 hipError_t launch_couple(const KArgs& ka, hipStream_t s) { return launch_gemm<GM_COUPLE, 3>(ka, ka.L.P - 1, ka.L.M, ka.L.M, s); }
-hipError_t launch_rhs_fwd(const KArgs& ka, hipStream_t s) { return launch_gemm<GM_RHS_FWD, 1>(ka, ka.L.P, ka.L.M, ka.R, s); }
-hipError_t launch_rhs_bwd(const KArgs& ka, hipStream_t s) { return launch_gemm<GM_RHS_BWD, 1>(ka, ka.L.P, ka.L.M, ka.R, s); }
 hipError_t launch_couple_rhs(const KArgs& ka, hipStream_t s) { return launch_gemm<GM_COUPLE_RHS, 1>(ka, ka.L.P - 1, ka.L.M, ka.R, s); }
 hipError_t launch_recover(const KArgs& ka, hipStream_t s) { return launch_gemm<GM_RECOVER, 1>(ka, ka.L.N, ka.L.M, ka.R, s); }
 
-size_t getrf_lds_bytes(int M) {
-    return sizeof(double) * ((size_t)NB * (M + 1) + (size_t)NB * M + 4) + sizeof(int) * (4 + NB + M);
-}
+static int getrf_rpl(int M) { return M <= 64 ? 1 : M <= 128 ? 2 : M <= 256 ? 4 : 8; }
+#ifndef BTD_GETRF_NB
+#define BTD_GETRF_NB 16
+#endif
+static int getrf_nb(int M) { return M <= 256 ? BTD_GETRF_NB : 8; }
+
+size_t getrf_lds_bytes(int M) { return getrf_lds_layout(M, getrf_nb(M)).total; }
 
 hipError_t launch_getrf(const KArgs& ka, hipStream_t s) {
-    const size_t lds = getrf_lds_bytes(ka.L.M);
-    hipLaunchKernelGGL(k_getrf, dim3(ka.L.P), dim3(256), lds, s, ka);
+    const int M = ka.L.M;
+    const size_t lds = getrf_lds_bytes(M);
+    dim3 grid(ka.L.P);
+    // 4 waves: the register panel of wave 0 needs more than the 256 registers per wave of an 8-wave group
+    switch (getrf_rpl(M)) {
+        case 1: hipLaunchKernelGGL((k_getrf<1, BTD_GETRF_NB, 256>), grid, dim3(256), lds, s, ka); break;
+        case 2: hipLaunchKernelGGL((k_getrf<2, BTD_GETRF_NB, 256>), grid, dim3(256), lds, s, ka); break;
+        case 4: hipLaunchKernelGGL((k_getrf<4, BTD_GETRF_NB, 256>), grid, dim3(256), lds, s, ka); break;
+        default: hipLaunchKernelGGL((k_getrf<8, 8, 256>), grid, dim3(256), lds, s, ka); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_diag_inv(const KArgs& ka, hipStream_t s) {
+    dim3 grid(cdiv(ka.L.M, DB), ka.L.P);
+    hipLaunchKernelGGL(k_diag_prep, grid, dim3(256), 0, s, ka);
     return hipGetLastError();
 }
 
 static int slab_width(int M) { return M <= 256 ? 32 : 16; }
 
-size_t getrs_lds_bytes(int M) {
-    const int sw = slab_width(M);
-    return sizeof(double) * (size_t)cdiv(M, 16) * 16 * (sw + 2);
+hipError_t launch_getrs(const KArgs& ka, hipStream_t s) {
+    const int M = ka.L.M, sw = slab_width(M);
+    dim3 grid(cdiv(2 * M, sw) * ka.L.P);
+    if (M <= 128) hipLaunchKernelGGL((k_getrs<32, 1>), grid, dim3(256), 0, s, ka);
+    else if (M <= 256) hipLaunchKernelGGL((k_getrs<32, 2>), grid, dim3(256), 0, s, ka);
+    else hipLaunchKernelGGL((k_getrs<16, 4>), grid, dim3(256), 0, s, ka);
+    return hipGetLastError();
 }
 
-hipError_t launch_getrs(const KArgs& ka, bool solve, hipStream_t s) {
-    const int M = ka.L.M, sw = slab_width(M);
-    const int ncols = solve ? ka.R : 2 * M;
-    dim3 grid(cdiv(ncols, sw), ka.L.P);
-    const size_t lds = getrs_lds_bytes(M);
-    if (sw == 32) {
-        if (solve) hipLaunchKernelGGL((k_getrs<32, true>), grid, dim3(256), lds, s, ka);
-        else hipLaunchKernelGGL((k_getrs<32, false>), grid, dim3(256), lds, s, ka);
-    } else {
-        if (solve) hipLaunchKernelGGL((k_getrs<16, true>), grid, dim3(256), lds, s, ka);
-        else hipLaunchKernelGGL((k_getrs<16, false>), grid, dim3(256), lds, s, ka);
+// Columns per workgroup and staging-panel width of the right-hand-side sweep
+// (LDS: three M x RB blocks plus an M x (KC+1) panel).
+static int chunk_solve_rb(int M, int R) {
+    const int rb = R <= 1 ? 1 : R <= 2 ? 2 : R <= 4 ? 4 : 8;
+    return M > 256 && rb > 4 ? 4 : rb;
+}
+static int chunk_solve_kc(int M) { return M <= 256 ? 32 : 16; }
+
+size_t chunk_solve_lds_bytes(int M, int R) {
+    const int rb = chunk_solve_rb(M, R), kc = chunk_solve_kc(M);
+    return sizeof(double) * (3 * (size_t)M * rb + (size_t)DB * rb + (size_t)DB * DB + (size_t)M * (kc + 1));
+}
+
+template <int KC>
+static void launch_chunk_solve_kc(const KArgs& ka, int rb, dim3 grid, size_t lds, hipStream_t s) {
+    switch (rb) {
+        case 1: hipLaunchKernelGGL((k_chunk_solve<1, KC>), grid, dim3(256), lds, s, ka); break;
+        case 2: hipLaunchKernelGGL((k_chunk_solve<2, KC>), grid, dim3(256), lds, s, ka); break;
+        case 4: hipLaunchKernelGGL((k_chunk_solve<4, KC>), grid, dim3(256), lds, s, ka); break;
+        default: hipLaunchKernelGGL((k_chunk_solve<8, KC>), grid, dim3(256), lds, s, ka); break;
     }
+}
+
+hipError_t launch_chunk_solve(const KArgs& ka, hipStream_t s) {
+    const int M = ka.L.M, rb = chunk_solve_rb(M, ka.R);
+    dim3 grid(ka.L.P, cdiv(ka.R, rb));
+    const size_t lds = chunk_solve_lds_bytes(M, ka.R);
+    if (chunk_solve_kc(M) == 32) launch_chunk_solve_kc<32>(ka, rb, grid, lds, s);
+    else launch_chunk_solve_kc<16>(ka, rb, grid, lds, s);
     return hipGetLastError();
 }
 
@@ -798,20 +1449,36 @@ hipError_t launch_residual(int N, int M, int R, const double* A, const double* B
 
 namespace btd {
 
+#ifdef BTD_PHASE_TIMING
+hipError_t read_phase_times(unsigned long long* out) {
+    hipError_t e = hipMemcpyFromSymbol(out, HIP_SYMBOL(g_phase), sizeof(unsigned long long) * 16);
+    unsigned long long z[16] = {0};
+    if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(g_phase), z, sizeof(z));
+    return e;
+}
+#endif
+
 // Kernels with more than 64 KiB of dynamic LDS must opt in (gfx950 has
 // 160 KiB per CU).
 hipError_t configure_kernels() {
     const int lds_max = 160 * 1024;
     hipError_t err;
-    err = hipFuncSetAttribute((const void*)k_getrf, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
-    if (err != hipSuccess) return err;
-    err = hipFuncSetAttribute((const void*)k_getrs<32, true>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
-    if (err != hipSuccess) return err;
-    err = hipFuncSetAttribute((const void*)k_getrs<32, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
-    if (err != hipSuccess) return err;
-    err = hipFuncSetAttribute((const void*)k_getrs<16, true>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
-    if (err != hipSuccess) return err;
-    return hipFuncSetAttribute((const void*)k_getrs<16, false>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
+    const void* getrf_kernels[] = {(const void*)k_getrf<1, BTD_GETRF_NB, 256>, (const void*)k_getrf<2, BTD_GETRF_NB, 256>,
+                                   (const void*)k_getrf<4, BTD_GETRF_NB, 256>, (const void*)k_getrf<8, 8, 256>};
+    for (const void* f : getrf_kernels) {
+        err = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
+        if (err != hipSuccess) return err;
+    }
+
+    const void* solve_kernels[] = {(const void*)k_chunk_solve<1, 32>, (const void*)k_chunk_solve<2, 32>,
+                                   (const void*)k_chunk_solve<4, 32>, (const void*)k_chunk_solve<8, 32>,
+                                   (const void*)k_chunk_solve<1, 16>, (const void*)k_chunk_solve<2, 16>,
+                                   (const void*)k_chunk_solve<4, 16>, (const void*)k_chunk_solve<8, 16>};
+    for (const void* f : solve_kernels) {
+        err = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
+        if (err != hipSuccess) return err;
+    }
+    return hipSuccess;
 }
 
 }  // namespace btd

@@ -77,7 +77,7 @@ size_t build_levels(const btd_desc_t* d, std::vector<LevelPlan>& lv) {
     int N = d->N, P = d->P, depth = d->depth;
     const int M = d->M;
     const size_t MM = (size_t)M * M;
-    const size_t nblk = (size_t)(M + 15) / 16;
+    const size_t nblk = (size_t)(M + 31) / 32;
     bool top = true;
     while (true) {
         LevelPlan L;
@@ -96,7 +96,7 @@ size_t build_levels(const btd_desc_t* d, std::vector<LevelPlan>& lv) {
             if (nk > L.nmax) L.nmax = nk;
         }
         L.off_LU = off; off = align_up(off + sizeof(double) * N * MM);
-        L.off_DI = off; off = align_up(off + sizeof(double) * N * nblk * 512);
+        L.off_DI = off; off = align_up(off + sizeof(double) * N * nblk * 2048);
         L.off_W = off; off = align_up(off + sizeof(double) * N * MM * 2);
         if (P > 1) {
             L.off_Z = off; off = align_up(off + sizeof(double) * N * MM * 2);
@@ -126,6 +126,25 @@ size_t solve_bytes_for(const std::vector<LevelPlan>& lv, int R) {
 }
 
 bool g_configured = false;
+
+// Event pairs around the launches of one kernel class (measurement only).
+struct Profiler {
+    int cls = -1;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+} g_prof;
+
+hipError_t timed(int cls, hipStream_t s, hipError_t (*fn)(const btd::KArgs&, hipStream_t), const btd::KArgs& ka) {
+    if (g_prof.cls != cls) return fn(ka, s);
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess) return hipErrorUnknown;
+    if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return hipErrorUnknown; }
+    (void)hipEventRecord(a, s);
+    hipError_t err = fn(ka, s);
+    (void)hipEventRecord(b, s);
+    g_prof.ev.emplace_back(a, b);
+    return err;
+}
+
 
 }  // namespace
 
@@ -180,16 +199,17 @@ int enqueue_factor(btd_plan_s* p, hipStream_t s) {
         BTD_TRY(btd::launch_write_ints((int*)(p->ws + LP.off_sep), LP.sep.data(), LP.P + 1, s));
         for (int t = 0; t < LP.nmax; ++t) {
             ka.step = t;
-            BTD_TRY(btd::launch_fwd_gemm(ka, s));
-            BTD_TRY(btd::launch_getrf(ka, s));
-            BTD_TRY(btd::launch_getrs(ka, false, s));
+            BTD_TRY(timed(BTD_KC_FWD_GEMM, s, btd::launch_fwd_gemm, ka));
+            BTD_TRY(timed(BTD_KC_GETRF, s, btd::launch_getrf, ka));
+            BTD_TRY(timed(BTD_KC_GETRF, s, btd::launch_diag_inv, ka));
+            BTD_TRY(timed(BTD_KC_GETRS_FACTOR, s, btd::launch_getrs, ka));
         }
         if (LP.P > 1) {
             for (int t = 0; t < LP.nmax; ++t) {
                 ka.step = t;
-                BTD_TRY(btd::launch_bwd_gemm(ka, s));
+                BTD_TRY(timed(BTD_KC_BWD_GEMM, s, btd::launch_bwd_gemm, ka));
             }
-            BTD_TRY(btd::launch_couple(ka, s));
+            BTD_TRY(timed(BTD_KC_COUPLE, s, btd::launch_couple, ka));
         }
     }
     return BTD_OK;
@@ -206,23 +226,15 @@ int enqueue_solve_level(const btd_plan_s* p, size_t l, int R, const double* F, d
     ka.F = F;
     ka.X = X;
     ka.status = p->status;
-    for (int t = 0; t < LP.nmax; ++t) {
-        ka.step = t;
-        BTD_TRY(btd::launch_rhs_fwd(ka, s));
-        BTD_TRY(btd::launch_getrs(ka, true, s));
-    }
-    for (int t = 1; t < LP.nmax; ++t) {
-        ka.step = t;
-        BTD_TRY(btd::launch_rhs_bwd(ka, s));
-    }
+    BTD_TRY(timed(BTD_KC_RHS_SWEEP, s, btd::launch_chunk_solve, ka));
     if (LP.P > 1) {
         double* Fc = (double*)(sws + sws_off);
         const size_t next = align_up(sws_off + sizeof(double) * (size_t)(LP.P - 1) * LP.M * R);
         ka.Fc = Fc;
-        BTD_TRY(btd::launch_couple_rhs(ka, s));
+        BTD_TRY(timed(BTD_KC_COUPLE_RHS, s, btd::launch_couple_rhs, ka));
         int rc = enqueue_solve_level(p, l + 1, R, Fc, Fc, sws, next, s);
         if (rc != BTD_OK) return rc;
-        BTD_TRY(btd::launch_recover(ka, s));
+        BTD_TRY(timed(BTD_KC_RECOVER, s, btd::launch_recover, ka));
     }
     return BTD_OK;
 }
@@ -236,6 +248,12 @@ int ensure_configured() {
 }
 
 }  // namespace
+
+#ifdef BTD_PHASE_TIMING
+namespace btd {
+hipError_t read_phase_times(unsigned long long* out);
+}
+#endif
 
 extern "C" {
 
@@ -328,7 +346,17 @@ int btd_residual(int32_t N, int32_t M, int32_t R, const double* A, const double*
     if (!F) return -8;
     if (!out) return -9;
     if (!work) return -10;
-    BTD_TRY(btd::launch_residual(N, M, R, A, B, C, X, F, out, (double*)work, (hipStream_t)stream));
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t a = nullptr, b = nullptr;
+    if (g_prof.cls == BTD_KC_RESIDUAL) {
+        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return BTD_ERR_LAUNCH;
+        (void)hipEventRecord(a, s);
+    }
+    BTD_TRY(btd::launch_residual(N, M, R, A, B, C, X, F, out, (double*)work, s));
+    if (a) {
+        (void)hipEventRecord(b, s);
+        g_prof.ev.emplace_back(a, b);
+    }
     return BTD_OK;
 }
 
@@ -375,6 +403,35 @@ int btd_default_coupling_parts(int32_t P, int32_t M, int32_t R) {
     if (P < 1 || M < 1 || R < 1) return -1;
     return coupling_parts(P, M, R);
 }
+
+int btd_profile_enable(int32_t kernel_class) {
+    if (kernel_class < -1 || kernel_class >= BTD_KC_COUNT) return -1;
+    g_prof.cls = kernel_class;
+    return BTD_OK;
+}
+
+int btd_profile_read(double* total_ms, int64_t* launches) {
+    double tot = 0.0;
+    int64_t n = 0;
+    int rc = BTD_OK;
+    for (auto& pr : g_prof.ev) {
+        float ms = 0.0f;
+        if (hipEventSynchronize(pr.second) != hipSuccess || hipEventElapsedTime(&ms, pr.first, pr.second) != hipSuccess)
+            rc = BTD_ERR_LAUNCH;
+        tot += ms;
+        ++n;
+        (void)hipEventDestroy(pr.first);
+        (void)hipEventDestroy(pr.second);
+    }
+    g_prof.ev.clear();
+    if (total_ms) *total_ms = tot;
+    if (launches) *launches = n;
+    return rc;
+}
+
+#ifdef BTD_PHASE_TIMING
+int btd_debug_phase_times(unsigned long long* out) { return btd::read_phase_times(out) == hipSuccess ? 0 : 3; }
+#endif
 
 void btd_plan_destroy(btd_plan_t plan) { delete plan; }
 

@@ -84,3 +84,30 @@ def test_coupling_parts_match_oracle():
     for P in range(1, 700):
         for M, R in ((16, 1), (128, 4), (256, 64)):
             assert btd.default_coupling_parts(P, M, R) == oracle.default_m(P, M, R), (P, M, R)
+
+
+@pytest.mark.parametrize("N,M,R,P,depth,seps", [(64, 16, 1, 4, 0, None), (64, 16, 3, 16, 1, None),
+                                                (40, 8, 2, 5, 0, [1, 15, 21, 33]), (300, 4, 2, 40, 2, None),
+                                                (57, 2, 1, 1, 0, None)])
+def test_flop_model_matches_oracle_counter(N, M, R, P, depth, seps):
+    """The benchmark's algorithmic FLOP model (LU convention) equals the
+    oracle's executed block-operation count converted to the same convention:
+    2/3 M^3 per inversion-as-LU, 2 M^3 per block product (including each
+    application of an inverse), 2 M^2 R per block x RHS product."""
+    from paper_1505_06864_amd import flops, inputs
+    A, B, C, F = inputs.diag_dominant(N, M, R, seed=7)
+    cnt = oracle.Counter()
+    oracle.dm_solve(A, B, C, F, P, seps=seps, depth=depth, counter=cnt)
+    fac, sol = flops.totals(N, M, R, P, depth, seps=seps)
+    want = 2.0 / 3.0 * M**3 * cnt.inv + 2.0 * M**3 * cnt.mm + 2.0 * M**2 * R * cnt.mr
+    assert abs((fac + sol) - want) <= 1e-9 * want
+
+
+def test_flop_model_large_workload():
+    """853.2 GFLOP factor and 2.65 GFLOP solve at N=4096, M=256, R=1, P=64
+    (depth 0); the plain Thomas algorithm (P=1) needs 320.6 + 1.61 GFLOP."""
+    from paper_1505_06864_amd import flops
+    fac, sol = flops.totals(4096, 256, 1, 64, 0)
+    assert abs(fac / 1e9 - 853.2) < 0.1 and abs(sol / 1e9 - 2.65) < 0.01
+    fac, sol = flops.totals(4096, 256, 1, 1, 0)
+    assert abs(fac / 1e9 - 320.6) < 0.1 and abs(sol / 1e9 - 1.61) < 0.01
