@@ -21,8 +21,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "block-tridiag solves/s + MFMA TFLOP/s vs peak (N=4096,M=256); p50/p99 latency"
-DEFAULT_P = 64
-DEFAULT_DEPTH = 1
+DEFAULT_P = 256
+DEFAULT_DEPTH = 2
 PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 (matrix and vector), vendor datasheet
 PEAK_HBM_GBS = 8000.0
 

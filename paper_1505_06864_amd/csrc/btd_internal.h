@@ -36,6 +36,7 @@ struct KArgs {
     double* X;                 // [N][M][R] level solution (may equal F)
     double* Fc;                // [P-1][M][R] coupling right-hand side / solution h
     unsigned long long* status;
+    int c0, nc;                // chunks c0 .. c0+nc-1 handled by a chunk-batched launch
 };
 
 struct IntChunk {

@@ -171,9 +171,9 @@ __device__ bool make_job(const KArgs& ka, int b, int part, Job& j) {
     j.m = M;
     j.n = M;
     if (MODE == GM_FWD) {
-        // chunk b, step t: D_i = A_i - B_i E_{i-1} (part 0, plus C_i -> W_i[:, :M]);
+        // chunk c0+b, step t: D_i = A_i - B_i E_{i-1} (part 0, plus C_i -> W_i[:, :M]);
         // Y_i = -B_i Y_{i-1} (part 1, chunks with a left spike).
-        const int k = b, t = ka.step;
+        const int k = ka.c0 + b, t = ka.step;
         const int r = chunk_first(L, k), e = chunk_last(L, k);
         if (t > e - r) return false;
         const int i = r + t;
@@ -190,8 +190,8 @@ __device__ bool make_job(const KArgs& ka, int b, int part, Job& j) {
         else { j.A1 = L.B + i * MM; j.lda1 = M; j.B1 = L.W + (i - 1) * MM * 2 + M; j.ldb1 = M2; j.k1 = M; }
         return true;
     } else if (MODE == GM_BWD) {
-        // chunk b, backward step s (row i = e - s): Z_L (part 0, k > 0), Z_R (part 1, k < P-1)
-        const int k = b, s = ka.step;
+        // chunk c0+b, backward step s (row i = e - s): Z_L (part 0, k > 0), Z_R (part 1, k < P-1)
+        const int k = ka.c0 + b, s = ka.step;
         const int r = chunk_first(L, k), e = chunk_last(L, k);
         if (s > e - r) return false;
         const int i = e - s;
@@ -619,7 +619,7 @@ __device__ __forceinline__ void lu_tile_store(double* a22, int M, int mt, int nt
 template <int RPL, int NB, int LU_THREADS>
 __global__ __launch_bounds__(LU_THREADS) void k_getrf(const KArgs ka) {
     const Level& L = ka.L;
-    const int k = blockIdx.x, t = ka.step;
+    const int k = ka.c0 + blockIdx.x, t = ka.step;
     const int r0 = chunk_first(L, k), e = chunk_last(L, k);
     if (t > e - r0) return;
     const int i = r0 + t;
@@ -772,7 +772,7 @@ __global__ __launch_bounds__(LU_THREADS) void k_getrf(const KArgs ka) {
 // y_b = inv(L_bb) w_b; likewise for U.
 __global__ __launch_bounds__(256) void k_diag_prep(const KArgs ka) {
     const Level& L = ka.L;
-    const int k = blockIdx.y, t = ka.step, M = L.M;
+    const int k = ka.c0 + blockIdx.y, t = ka.step, M = L.M;
     const int r0 = chunk_first(L, k), e = chunk_last(L, k);
     if (t > e - r0) return;
     const int i = r0 + t;
@@ -944,7 +944,10 @@ __device__ void getrs_slab(const double* __restrict__ lu, const double* __restri
     auto valid = [&](int col) {
         return col < ncols && ((col >= valid_lo && col < valid_hi) || (col >= valid2_lo && col < valid2_hi));
     };
-    // the slab, permuted, into accumulator registers
+    // the slab, permuted (row indices staged in LDS), into accumulator registers
+    int* sperm = (int*)(xb + 2 * DB * PX);
+    for (int r = tid; r < M; r += 256) sperm[r] = perm[r];
+    __syncthreads();
     v4d x[BPW][2][NSUB];
 #pragma unroll
     for (int jb = 0; jb < BPW; ++jb)
@@ -957,7 +960,7 @@ __device__ void getrs_slab(const double* __restrict__ lu, const double* __restri
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int row = (w + 4 * jb) * DB + tr * 16 + (lane >> 4) + 4 * v;
-                    x[jb][tr][tc][v] = (row < M && cv) ? X[(size_t)perm[row] * ld + col] : 0.0;
+                    x[jb][tr][tc][v] = (row < M && cv) ? X[(size_t)sperm[row] * ld + col] : 0.0;
                 }
             }
     double ops[BPW][2][DB / 4];
@@ -996,19 +999,23 @@ __device__ void getrs_slab(const double* __restrict__ lu, const double* __restri
                     for (int kk = 0; kk < DB / 4; ++kk) cur[jb][tr][kk] = ops[jb][tr][kk];
             if (step + 1 < nblk) trsm_load_ops<SW, BPW>(lu, M, nblk, dir, dir == 0 ? step + 1 : nblk - 2 - step, w, lane, ops);
             else if (dir == 0) trsm_load_ops<SW, BPW>(lu, M, nblk, 1, nblk - 1, w, lane, ops);
+            // the published block as B operands, read once for all of this wave's blocks
+            double bo[NSUB][DB / 4];
+#pragma unroll
+            for (int tc = 0; tc < NSUB; ++tc)
+#pragma unroll
+                for (int kk = 0; kk < DB / 4; ++kk) bo[tc][kk] = xt[((lane >> 4) * 8 + kk) * PX + tc * 16 + (lane & 15)];
 #pragma unroll
             for (int jb = 0; jb < BPW; ++jb) {
                 const int bp = w + 4 * jb;
                 if (bp < nblk && (dir == 0 ? bp > b : bp < b)) {
 #pragma unroll
-                    for (int tr = 0; tr < 2; ++tr)
+                    for (int kk = 0; kk < DB / 4; ++kk)
 #pragma unroll
-                        for (int tc = 0; tc < NSUB; ++tc)
+                        for (int tr = 0; tr < 2; ++tr)
 #pragma unroll
-                            for (int kk = 0; kk < DB / 4; ++kk)
-                                x[jb][tr][tc] = mfma4(cur[jb][tr][kk],
-                                                      xt[((lane >> 4) * 8 + kk) * PX + tc * 16 + (lane & 15)],
-                                                      x[jb][tr][tc]);
+                            for (int tc = 0; tc < NSUB; ++tc)
+                                x[jb][tr][tc] = mfma4(cur[jb][tr][kk], bo[tc][kk], x[jb][tr][tc]);
                 }
             }
             buf ^= 1;
@@ -1044,12 +1051,12 @@ __device__ void getrs_slab(const double* __restrict__ lu, const double* __restri
 // RHS = W_i = [C_i | -B_i Y_{i-1}] of chunk blockIdx.y at step t.
 template <int SW, int BPW>
 __global__ __launch_bounds__(256) void k_getrs(const KArgs ka) {
-    __shared__ double xb[2 * DB * (SW + 2)];
+    __shared__ double xb[2 * DB * (SW + 2) + BTD_MAX_M / 2];  // two publish tiles + the row permutation
     __shared__ double ownb[4 * DB * (SW + 2)];
     const Level& L = ka.L;
     const int M = L.M, nslab = (2 * M + SW - 1) / SW;
     const int lid = xcd_logical_id(blockIdx.x, gridDim.x);
-    const int k = lid / nslab, t = ka.step;
+    const int k = ka.c0 + lid / nslab, t = ka.step;
     const int r = chunk_first(L, k), e = chunk_last(L, k);
     if (t > e - r) return;
     const int i = r + t;
@@ -1342,8 +1349,8 @@ static hipError_t launch_gemm(const KArgs& ka, int batch, int m, int n, hipStrea
     return hipGetLastError();
 }
 
-hipError_t launch_fwd_gemm(const KArgs& ka, hipStream_t s) { return launch_gemm<GM_FWD, 2>(ka, ka.L.P, ka.L.M, ka.L.M, s); }
-hipError_t launch_bwd_gemm(const KArgs& ka, hipStream_t s) { return launch_gemm<GM_BWD, 2>(ka, ka.L.P, ka.L.M, ka.L.M, s); }
+hipError_t launch_fwd_gemm(const KArgs& ka, hipStream_t s) { return launch_gemm<GM_FWD, 2>(ka, ka.nc, ka.L.M, ka.L.M, s); }
+hipError_t launch_bwd_gemm(const KArgs& ka, hipStream_t s) { return launch_gemm<GM_BWD, 2>(ka, ka.nc, ka.L.M, ka.L.M, s); }
 hipError_t launch_couple(const KArgs& ka, hipStream_t s) { return launch_gemm<GM_COUPLE, 3>(ka, ka.L.P - 1, ka.L.M, ka.L.M, s); }
 hipError_t launch_couple_rhs(const KArgs& ka, hipStream_t s) { return launch_gemm<GM_COUPLE_RHS, 1>(ka, ka.L.P - 1, ka.L.M, ka.R, s); }
 hipError_t launch_recover(const KArgs& ka, hipStream_t s) { return launch_gemm<GM_RECOVER, 1>(ka, ka.L.N, ka.L.M, ka.R, s); }
@@ -1359,7 +1366,7 @@ size_t getrf_lds_bytes(int M) { return getrf_lds_layout(M, getrf_nb(M)).total; }
 hipError_t launch_getrf(const KArgs& ka, hipStream_t s) {
     const int M = ka.L.M;
     const size_t lds = getrf_lds_bytes(M);
-    dim3 grid(ka.L.P);
+    dim3 grid(ka.nc);
     // 4 waves: the register panel of wave 0 needs more than the 256 registers per wave of an 8-wave group
     switch (getrf_rpl(M)) {
         case 1: hipLaunchKernelGGL((k_getrf<1, BTD_GETRF_NB, 256>), grid, dim3(256), lds, s, ka); break;
@@ -1371,7 +1378,7 @@ hipError_t launch_getrf(const KArgs& ka, hipStream_t s) {
 }
 
 hipError_t launch_diag_inv(const KArgs& ka, hipStream_t s) {
-    dim3 grid(cdiv(ka.L.M, DB), ka.L.P);
+    dim3 grid(cdiv(ka.L.M, DB), ka.nc);
     hipLaunchKernelGGL(k_diag_prep, grid, dim3(256), 0, s, ka);
     return hipGetLastError();
 }
@@ -1380,7 +1387,7 @@ static int slab_width(int M) { return M <= 256 ? 32 : 16; }
 
 hipError_t launch_getrs(const KArgs& ka, hipStream_t s) {
     const int M = ka.L.M, sw = slab_width(M);
-    dim3 grid(cdiv(2 * M, sw) * ka.L.P);
+    dim3 grid(cdiv(2 * M, sw) * ka.nc);
     if (M <= 128) hipLaunchKernelGGL((k_getrs<32, 1>), grid, dim3(256), 0, s, ka);
     else if (M <= 256) hipLaunchKernelGGL((k_getrs<32, 2>), grid, dim3(256), 0, s, ka);
     else hipLaunchKernelGGL((k_getrs<16, 4>), grid, dim3(256), 0, s, ka);

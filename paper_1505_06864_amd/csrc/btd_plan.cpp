@@ -127,6 +127,39 @@ size_t solve_bytes_for(const std::vector<LevelPlan>& lv, int R) {
 
 bool g_configured = false;
 
+// Side streams (default priority) of the current device: the chunks of a
+// level are split into groups whose sweeps run on their own streams, forked
+// from and joined back to the caller's stream with events, so that one
+// group's LU launches overlap the other groups' GEMM and TRSM launches.
+constexpr int kMaxGroups = 4;
+struct StreamPool {
+    int device = -1;
+    hipStream_t s[kMaxGroups] = {};
+    hipEvent_t fork = nullptr, join[kMaxGroups] = {};
+};
+constexpr int kMaxDevices = 16;
+StreamPool g_pools[kMaxDevices];
+
+StreamPool* stream_pool() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    StreamPool& p = g_pools[dev];
+    if (p.device == dev) return &p;
+    for (int g = 0; g < kMaxGroups; ++g) {
+        if (hipStreamCreateWithFlags(&p.s[g], hipStreamNonBlocking) != hipSuccess) return nullptr;
+        if (hipEventCreateWithFlags(&p.join[g], hipEventDisableTiming) != hipSuccess) return nullptr;
+    }
+    if (hipEventCreateWithFlags(&p.fork, hipEventDisableTiming) != hipSuccess) return nullptr;
+    p.device = dev;
+    return &p;
+}
+
+// Groups for a level of P chunks: at least 8 chunks per group.
+int chunk_groups(int P) {
+    int g = P / 8;
+    return g < 1 ? 1 : (g > kMaxGroups ? kMaxGroups : g);
+}
+
 // Event pairs around the launches of one kernel class (measurement only).
 struct Profiler {
     int cls = -1;
@@ -196,21 +229,48 @@ int enqueue_factor(btd_plan_s* p, hipStream_t s) {
         std::memset(&ka, 0, sizeof(ka));
         ka.L = p->level_dev((int)l);
         ka.status = p->status;
+        ka.c0 = 0;
+        ka.nc = LP.P;
         BTD_TRY(btd::launch_write_ints((int*)(p->ws + LP.off_sep), LP.sep.data(), LP.P + 1, s));
+        // chunk groups, each on its own stream (one group: the caller's stream)
+        int G = chunk_groups(LP.P);
+        StreamPool* pool = G > 1 ? stream_pool() : nullptr;
+        if (!pool) G = 1;
+        hipStream_t gs[kMaxGroups];
+        KArgs gk[kMaxGroups];
+        for (int g = 0; g < G; ++g) {
+            gs[g] = G > 1 ? pool->s[g] : s;
+            gk[g] = ka;
+            gk[g].c0 = (int)((int64_t)LP.P * g / G);
+            gk[g].nc = (int)((int64_t)LP.P * (g + 1) / G) - gk[g].c0;
+        }
+        if (G > 1) {
+            BTD_TRY(hipEventRecord(pool->fork, s));
+            for (int g = 0; g < G; ++g) BTD_TRY(hipStreamWaitEvent(gs[g], pool->fork, 0));
+        }
         for (int t = 0; t < LP.nmax; ++t) {
-            ka.step = t;
-            BTD_TRY(timed(BTD_KC_FWD_GEMM, s, btd::launch_fwd_gemm, ka));
-            BTD_TRY(timed(BTD_KC_GETRF, s, btd::launch_getrf, ka));
-            BTD_TRY(timed(BTD_KC_GETRF, s, btd::launch_diag_inv, ka));
-            BTD_TRY(timed(BTD_KC_GETRS_FACTOR, s, btd::launch_getrs, ka));
+            for (int g = 0; g < G; ++g) {
+                gk[g].step = t;
+                BTD_TRY(timed(BTD_KC_FWD_GEMM, gs[g], btd::launch_fwd_gemm, gk[g]));
+                BTD_TRY(timed(BTD_KC_GETRF, gs[g], btd::launch_getrf, gk[g]));
+                BTD_TRY(timed(BTD_KC_GETRF, gs[g], btd::launch_diag_inv, gk[g]));
+                BTD_TRY(timed(BTD_KC_GETRS_FACTOR, gs[g], btd::launch_getrs, gk[g]));
+            }
         }
         if (LP.P > 1) {
-            for (int t = 0; t < LP.nmax; ++t) {
-                ka.step = t;
-                BTD_TRY(timed(BTD_KC_BWD_GEMM, s, btd::launch_bwd_gemm, ka));
-            }
-            BTD_TRY(timed(BTD_KC_COUPLE, s, btd::launch_couple, ka));
+            for (int t = 0; t < LP.nmax; ++t)
+                for (int g = 0; g < G; ++g) {
+                    gk[g].step = t;
+                    BTD_TRY(timed(BTD_KC_BWD_GEMM, gs[g], btd::launch_bwd_gemm, gk[g]));
+                }
         }
+        if (G > 1) {
+            for (int g = 0; g < G; ++g) {
+                BTD_TRY(hipEventRecord(pool->join[g], gs[g]));
+                BTD_TRY(hipStreamWaitEvent(s, pool->join[g], 0));
+            }
+        }
+        if (LP.P > 1) BTD_TRY(timed(BTD_KC_COUPLE, s, btd::launch_couple, ka));
     }
     return BTD_OK;
 }
@@ -226,6 +286,8 @@ int enqueue_solve_level(const btd_plan_s* p, size_t l, int R, const double* F, d
     ka.F = F;
     ka.X = X;
     ka.status = p->status;
+    ka.c0 = 0;
+    ka.nc = LP.P;
     BTD_TRY(timed(BTD_KC_RHS_SWEEP, s, btd::launch_chunk_solve, ka));
     if (LP.P > 1) {
         double* Fc = (double*)(sws + sws_off);
