@@ -6,8 +6,8 @@ coupling factor), solve (right-hand-side sweeps, coupling solve, recovery)
 and the on-device FP64 residual check.  Prints ONE JSON line.
 
 Default workload: dense diagonally dominant blocks, N=4096 block rows of
-M=256 (diagonal shift 1.5), R=1 right-hand side, FP64, P=64 subsystems,
-recursion depth 1 on the coupling system.
+M=256 (diagonal shift 1.5), R=1 right-hand side, FP64, P=256 subsystems,
+the coupling system solved by the same method two levels deep.
 """
 import argparse
 import json
@@ -46,7 +46,22 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-rows", type=int, default=None)
     ap.add_argument("--roofline-class", default="auto")
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="only run a plain device-to-device copy of this many MiB three times (calibrates "
+                         "the HBM byte counters against a kernel of known traffic) and exit")
     return ap.parse_args()
+
+
+def copy_calibration(torch, mib):
+    """A plain copy kernel of known size: reads and writes mib MiB per launch."""
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_per_launch": n * 8, "launches": 3}), flush=True)
 
 
 def make_inputs(torch, name, dev):
@@ -139,6 +154,29 @@ def cpu_baseline(host_inputs, P, depth, rows, workload):
                        f"scaled to the full workload by the algorithmic-FLOP ratio {f_full / f_s:.1f}")}
 
 
+def recorded_traffic(kclass, workload, P, depth):
+    """HBM bytes per launch of a kernel class from the committed rocprofv3
+    counter summary (FETCH_SIZE + WRITE_SIZE, each scaled against a plain copy
+    kernel), or None when there is none for this workload and plan or the
+    kernel source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{kclass}_{workload}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if line.startswith("#") or ":" not in line:
+            continue
+        k, v = line.split(":", 1)
+        kv[k.strip()] = v.strip()
+    src = os.path.join(ROOT, "paper_1505_06864_amd", "csrc", "btd_kernels.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if (kv.get("kernel_source_sha256") != sha or kv.get("kernel_class") != kclass
+            or kv.get("P") != str(P) or kv.get("depth") != str(depth)):
+        return None
+    return float(kv["hbm_bytes_per_launch"])
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -148,6 +186,9 @@ def main():
     import numpy as np
     import torch
 
+    if args.copy_calib_mib > 0:
+        copy_calibration(torch, args.copy_calib_mib)
+        return
     from paper_1505_06864_amd import btd, flops
     dev = torch.device("cuda:0")
     N, M, R, gen = WORKLOADS[args.workload]
@@ -193,7 +234,9 @@ def main():
 
     fac, sol = flops.totals(N, M, R, P, depth, R)
     ms_step = wall * 1e3 / args.steps
-    dom_flops_per_launch = per[dom][0] / max(per[dom][1], 1)
+    # per launch = the class's algorithmic FLOPs over the launches actually made (chunk groups on
+    # several streams split one step into several launches)
+    dom_flops_per_launch = per[dom][0] * args.steps / max(dom_n, 1)
     dom_avg_ms = dom_ms / max(dom_n, 1)
     achieved = dom_flops_per_launch / (dom_avg_ms * 1e-3) / 1e12
     tflops = (fac + sol) / (ms_step * 1e-3) / 1e12
@@ -220,7 +263,8 @@ def main():
         "residual_max": resid,
         "kernel_ms_per_step": {c: round(v, 3) for c, v in class_ms.items()},
         "roofline": {"kernel": dom, "bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
+                     "traffic": recorded_traffic(dom, args.workload, P, depth),
                      "avg_launch_ms": dom_avg_ms, "launches": dom_n,
                      "gflop_per_launch": dom_flops_per_launch / 1e9},
     }

@@ -199,7 +199,8 @@ int btd_default_coupling_parts(int32_t P, int32_t M, int32_t R);
 #define BTD_KC_COUPLE_RHS 6   /* coupling right-hand side (Eq. e2311)                      */
 #define BTD_KC_RECOVER 7      /* X = z - Z_L h^{k-1} - Z_R h^k (Eq. endSolution)           */
 #define BTD_KC_RESIDUAL 8     /* residual check                                            */
-#define BTD_KC_COUNT 9
+#define BTD_KC_DIAG_PREP 9    /* inverses of the 32x32 diagonal blocks of L and U, scaled off-diagonal blocks */
+#define BTD_KC_COUNT 10
 int btd_profile_enable(int32_t kernel_class);
 int btd_profile_read(double *total_ms, int64_t *launches);
 

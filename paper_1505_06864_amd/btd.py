@@ -28,7 +28,7 @@ EXPORTS = ("btd_workspace_bytes", "btd_factor", "btd_solve", "btd_solve_batch", 
 
 # Kernel classes of btd_profile_enable (BTD_KC_*).
 KERNEL_CLASSES = ("fwd_gemm", "getrf", "getrs_factor", "bwd_gemm", "couple", "rhs_sweep", "couple_rhs",
-                  "recover", "residual")
+                  "recover", "residual", "diag_prep")
 
 
 class Desc(ctypes.Structure):

@@ -253,7 +253,7 @@ int enqueue_factor(btd_plan_s* p, hipStream_t s) {
                 gk[g].step = t;
                 BTD_TRY(timed(BTD_KC_FWD_GEMM, gs[g], btd::launch_fwd_gemm, gk[g]));
                 BTD_TRY(timed(BTD_KC_GETRF, gs[g], btd::launch_getrf, gk[g]));
-                BTD_TRY(timed(BTD_KC_GETRF, gs[g], btd::launch_diag_inv, gk[g]));
+                BTD_TRY(timed(BTD_KC_DIAG_PREP, gs[g], btd::launch_diag_inv, gk[g]));
                 BTD_TRY(timed(BTD_KC_GETRS_FACTOR, gs[g], btd::launch_getrs, gk[g]));
             }
         }

@@ -34,7 +34,13 @@ def chunk_sizes(N, P, seps):
 
 
 def per_class(N, M, R, P, depth=0, max_nrhs=None, seps=None):
-    """Dict kernel class -> (total algorithmic FLOPs, number of launches)."""
+    """Dict kernel class -> (total algorithmic FLOPs, number of launch steps).
+
+    The launch-step count is that of one stream; when the plan splits a
+    level's chunks into groups on several streams each step is that many
+    launches.  diag_prep (inverses of the 32x32 diagonal blocks of the LU
+    factors, used by the triangular solves) is a reformulation of the
+    triangular solves, not an operation of the method: 0 algorithmic FLOPs."""
     max_nrhs = max_nrhs or R
     M3, M2R = float(M) ** 3, float(M) ** 2 * R
     tot = {c: 0.0 for c in CLASSES}
@@ -60,6 +66,7 @@ def per_class(N, M, R, P, depth=0, max_nrhs=None, seps=None):
         launches["fwd_gemm"] += nmax
         launches["getrf"] += nmax
         launches["getrs_factor"] += nmax
+        launches["diag_prep"] += nmax
         launches["rhs_sweep"] += 1
         if Pl > 1:
             launches["bwd_gemm"] += nmax
