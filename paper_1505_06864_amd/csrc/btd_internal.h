@@ -19,6 +19,7 @@ namespace btd {
 struct Level {
     const double *A, *B, *C;  // [N][M][M]
     double* LU;               // [N][M][M]   LU factors of D_i (unit L below, U on/above the diagonal)
+    double* Dw;               // [P][M][M]   per-chunk working copy of the D_i being factored
     double* DI;               // [N][ceil(M/32)][2][32][32] inverses of the 32x32 diagonal blocks of L and U
     double* W;                // [N][M][2M]  [E_i | Y_i]: E_i = D_i^{-1} C_i, Y = forward sweep of the left spike
     double* Z;                // [N][M][2M]  [Z_L | Z_R] spikes (P > 1)

@@ -171,14 +171,15 @@ __device__ bool make_job(const KArgs& ka, int b, int part, Job& j) {
     j.m = M;
     j.n = M;
     if (MODE == GM_FWD) {
-        // chunk c0+b, step t: D_i = A_i - B_i E_{i-1} (part 0, plus C_i -> W_i[:, :M]);
+        // chunk c0+b, step t: D_i = A_i - B_i E_{i-1} into the chunk's working copy
+        // (part 0, plus C_i -> W_i[:, :M]);
         // Y_i = -B_i Y_{i-1} (part 1, chunks with a left spike).
         const int k = ka.c0 + b, t = ka.step;
         const int r = chunk_first(L, k), e = chunk_last(L, k);
         if (t > e - r) return false;
         const int i = r + t;
         if (part == 0) {
-            j.Out = L.LU + i * MM; j.ldo = M;
+            j.Out = L.Dw + k * MM; j.ldo = M;
             j.Cin = L.A + i * MM; j.ldc = M;
             if (t > 0) { j.A1 = L.B + i * MM; j.lda1 = M; j.B1 = L.W + (i - 1) * MM * 2; j.ldb1 = M2; j.k1 = M; }
             if (i != L.N - 1) { j.CopyIn = L.C + i * MM; j.ldci = M; j.CopyOut = L.W + i * MM * 2; j.ldco = M2; }
@@ -373,389 +374,352 @@ __global__ __launch_bounds__(256) void k_gemm(const KArgs ka, int tiles_m, int t
 
 // ------------------------------------------------------------------ LU
 //
-// One workgroup (8 waves, or 4 when the register panel needs the larger
-// per-wave register budget) per diagonal block D_i: blocked
-// right-looking LU with partial pivoting (row interchanges, ties to the
-// first maximum in the current row order), panels of NB columns, with
-// look-ahead:
-//   A(p)  wave 0 factors panel p held in its registers (lane l owns panel
-//         rows l, l+64, ...); the pivot search is a DPP/readlane reduction,
-//         rows stay in their lanes and only their positions change, and
-//         wave 0 finishes with inv(L11) of the panel.
-//   B(p)  all threads: the panel's interchanges are applied to the other
-//         columns as one gather, and U12 = inv(L11) A12 on MFMA.
-//   C(p)  A22 -= L21 U12 on MFMA: first the columns of panel p+1 (all
-//         waves), then wave 0 runs A(p+1) while the other waves update the
-//         rest.
-// The diagonal-block inverses for the triangular solves come from a
-// separate kernel.
+// LU with partial pivoting of every D_i factored at this step, one
+// workgroup of NT threads per block (NT >= M), right-looking with panels of
+// NB columns, on the chunk's working copy of D_i.  Rows never move in the
+// working copy: thread t owns row t.  As soon as a panel's NB pivot rows are
+// known and eliminated they are final and are written to the factor array
+// in pivot order (their multipliers from the working copy, the panel part
+// and U12 from LDS), so the factors come out in pivot order with
+// perm[q] = the row of D_i chosen as q-th pivot.
+//   panel   every thread keeps the NB panel values of its row in registers.
+//           Per column: each wave finds its largest |value| among the rows
+//           not chosen yet (DPP reduction) and publishes value, row and the
+//           rest of that row to a double-buffered LDS slot; after one
+//           barrier every thread takes the overall maximum (lowest row on
+//           ties; a non-finite value always wins so that it is reported)
+//           and eliminates with the pivot row read back from the slot.
+//   U12     inv(L11) of the panel's unit lower triangle, then
+//           U12 = inv(L11) A12 on MFMA for the pivot rows right of the panel.
+//   update  A22 -= L21 U12 on MFMA over the rows not chosen yet, which are
+//           listed contiguously, in 32 x 32 tiles spread over the waves.
 constexpr int DB = 32;                 // diagonal block of the triangular solves
 constexpr int DI_STRIDE = 2 * DB * DB; // doubles per diagonal block (L inverse, then U inverse)
 
-struct GetrfLds {
-    int PM, UM;
-    size_t pan, us, il, rowbuf, list, srcmap, naff, sperm, total;
+__device__ __forceinline__ void wave_lds_sync() { __asm__ volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
+struct LuLds {
+    int LP, UP, TP;   // pitches (doubles) of the multiplier rows, U12 rows, inv(L11) rows
+    size_t lb, ub, tb, cval, crow, cidx, piv, list, wcnt, total;
 };
 
-__host__ __device__ inline GetrfLds getrf_lds_layout(int M, int NB) {
-    GetrfLds l;
-    l.PM = M + 1;
-    l.UM = M;
+// LP = NB + 2 and UP = 16 (mod 32) keep the MFMA operand reads of one
+// 32-lane half free of bank conflicts for consecutive rows.
+__host__ __device__ inline LuLds lu_lds_layout(int M, int NT, int NB) {
+    LuLds l;
+    const int NW = NT / 64;
+    l.LP = NB + 2;
+    l.TP = NB + 2;
+    const int w2 = M > NB ? M - NB : 1;
+    l.UP = ((w2 + 31) / 32) * 32 + 16;
     size_t off = 0;
-    l.pan = off; off += sizeof(double) * 2 * (size_t)NB * l.PM;   // two panel buffers
-    l.us = off; off += sizeof(double) * (size_t)NB * l.UM;   // rows j0..j0+nb-1 of every column outside the panel
-    l.il = off; off += sizeof(double) * 16 * 16;
-    l.rowbuf = off; off += sizeof(double) * (2 * NB + 2);
-    l.list = off; off += sizeof(int) * 2 * NB;
-    l.srcmap = off; off += sizeof(int) * NB;
-    l.naff = off; off += sizeof(int) * 4;
-    l.sperm = off; off += sizeof(int) * (size_t)M;
-    l.total = off;
+    l.lb = off; off += sizeof(double) * (size_t)NT * l.LP;
+    l.ub = off; off += sizeof(double) * (size_t)NB * l.UP;
+    l.tb = off; off += sizeof(double) * (size_t)NB * l.TP;
+    l.cval = off; off += sizeof(double) * 2 * NW;
+    l.crow = off; off += sizeof(double) * 2 * NW * (size_t)NB;
+    l.cidx = off; off += sizeof(int) * 2 * NW;
+    l.piv = off; off += sizeof(int) * NB;
+    l.list = off; off += sizeof(int) * (size_t)NT;
+    l.wcnt = off; off += sizeof(int) * (NW + 1);
+    l.total = (off + 15) & ~(size_t)15;
     return l;
 }
 
-__device__ __forceinline__ void wave_lds_sync() { __asm__ volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
-
-// One column step JJ of the register-resident panel factorisation (wave 0),
-// expanded at compile time so every register index is static.  Rows never
-// move between lanes: pos[s] is the current position (0-based inside the
-// panel) of the row held in slot s, so a row interchange only swaps two
-// positions.  The pivot is the largest |value| among rows at positions >= JJ,
-// the lowest position on ties.  The pivot row is broadcast with readlane
-// (only the columns still needed), multipliers are scaled by the reciprocal
-// of the pivot, and the update is branch-free (inactive rows use a zero
-// multiplier).  The pivot value is recorded in rowbuf[JJ] (lane 0) for the
-// status check after the panel; rowbuf[NB..2NB) carries the pivot row.
-template <int RPL, int NB, int JJ>
-__device__ __forceinline__ void panel_column(double (&p)[RPL][NB], int (&pos)[RPL], int h, int lane,
-                                             double* rowbuf) {
-    double* piv_out = rowbuf;
-    if constexpr (JJ < NB) {
-        double bv = -1.0;
-#pragma unroll
-        for (int s = 0; s < RPL; ++s) {
-            const double v = fabs(p[s][JJ]);
-            bv = (pos[s] >= JJ && pos[s] < h && v > bv) ? v : bv;
-        }
-        const double mx = wave_max(bv);
-        // lowest position holding the maximum
-        int cand = 0x7fffffff;
-#pragma unroll
-        for (int s = 0; s < RPL; ++s)
-            cand = (pos[s] >= JJ && pos[s] < h && fabs(p[s][JJ]) == mx && pos[s] < cand) ? pos[s] : cand;
-        const int ppos = wave_min_int(cand);
-        const bool found = ppos != 0x7fffffff;
-        // the winning lane publishes the rest of the pivot row through LDS
-#pragma unroll
-        for (int s = 0; s < RPL; ++s)
-            if (pos[s] == ppos) {
-#pragma unroll
-                for (int c = JJ; c < NB; ++c) rowbuf[NB + c] = p[s][c];
-            }
-        wave_lds_sync();
-        double prow[NB];
-#pragma unroll
-        for (int c = 0; c < NB; ++c) prow[c] = (c >= JJ && found) ? rowbuf[NB + c] : 0.0;
-        const int pj = found ? ppos : JJ;
-#pragma unroll
-        for (int s = 0; s < RPL; ++s) {
-            const int q = pos[s];
-            pos[s] = (q == JJ) ? pj : (q == pj ? JJ : q);
-        }
-        const double piv = found ? prow[JJ] : __longlong_as_double(0x7ff8000000000000ll);
-        if (lane == 0) piv_out[JJ] = piv;
-        const double rp = (piv != 0.0 && found) ? 1.0 / piv : 0.0;
-#pragma unroll
-        for (int s = 0; s < RPL; ++s) {
-            const bool act = pos[s] > JJ && pos[s] < h;
-            const double l = act ? p[s][JJ] * rp : 0.0;
-            p[s][JJ] = act ? l : p[s][JJ];
-#pragma unroll
-            for (int c = JJ + 1; c < NB; ++c) p[s][c] = fma(-l, prow[c], p[s][c]);
-        }
-        wave_lds_sync();
-        panel_column<RPL, NB, JJ + 1>(p, pos, h, lane, piv_out);
-    }
-}
-
-// A(p): wave 0 factors the panel at column j0 (nb columns, h rows) held in
-// registers, writes the factors to global memory and to the LDS panel buffer
-// `pan` (column-major, positions as rows), the map from the first nb
-// positions to their source rows, the list of rows displaced to positions
-// >= nb (at most one per column step, so at most nb), the running
-// permutation, and inv(L11) (16 x 16, zero-padded) into `il`.
-template <int RPL, int NB>
-__device__ __forceinline__ void lu_panel(double* a, int M, int j0, int PM, double* pan, double* il, double* rowbuf,
-                                         int* list, int* srcmap, int* naff_s, int* sperm, int lane, int& fail_code,
-                                         int& fail_col) {
-    const int nb = min(NB, M - j0), h = M - j0;
-    double p[RPL][NB];
-    int pos[RPL];
-#pragma unroll
-    for (int s = 0; s < RPL; ++s) {
-        const int r = s * 64 + lane;
-        pos[s] = r;
-#pragma unroll
-        for (int c = 0; c < NB; ++c)
-            p[s][c] = (r < h && c < nb) ? a[(size_t)(j0 + r) * M + j0 + c] : ((r == c) ? 1.0 : 0.0);
-    }
-    // rows past the end of the matrix are padded with the identity, so a
-    // ragged last panel needs no column guards
-    panel_column<RPL, NB, 0>(p, pos, max(h, NB), lane, rowbuf);
-    wave_lds_sync();
-    if (fail_code == 0) {
-        for (int jj = 0; jj < nb; ++jj) {
-            const double pv = rowbuf[jj];
-            if (!isfinite(pv)) { fail_code = BTD_ERR_NONFINITE_; fail_col = j0 + jj; break; }
-            if (pv == 0.0) { fail_code = BTD_ERR_SINGULAR_; fail_col = j0 + jj; break; }
-        }
-    }
-    int cnt = 0;
-#pragma unroll
-    for (int s = 0; s < RPL; ++s) {
-        const int r = s * 64 + lane, q = pos[s];
-        if (q < h) {
-#pragma unroll
-            for (int c = 0; c < NB; ++c)
-                if (c < nb) {
-                    a[(size_t)(j0 + q) * M + j0 + c] = p[s][c];
-                    pan[c * PM + q] = p[s][c];
-                }
-            if (q < nb) srcmap[q] = r;
-        }
-        const bool aff = (q < h) && (q >= nb) && (q != r);
-        const unsigned long long mask = __ballot(aff);
-        const int at = cnt + __popcll(mask & ((1ull << lane) - 1ull));
-        if (aff) { list[2 * at] = q; list[2 * at + 1] = r; }
-        cnt += __popcll(mask);
-    }
-    int tmp[RPL];
-#pragma unroll
-    for (int s = 0; s < RPL; ++s) {
-        const int r = s * 64 + lane;
-        tmp[s] = (r < h) ? sperm[j0 + r] : 0;
-    }
-    wave_lds_sync();
-#pragma unroll
-    for (int s = 0; s < RPL; ++s)
-        if (pos[s] < h) sperm[j0 + pos[s]] = tmp[s];
-    if (lane == 0) naff_s[0] = cnt;
-    // inv(L11), zero-padded to 16 x 16: lane jc < 16 computes column jc
-    if (lane < 16) {
-        const int jc = lane;
-        double x[16];
-#pragma unroll
-        for (int rr = 0; rr < 16; ++rr) {
-            double s = (rr == jc) ? 1.0 : 0.0;
-#pragma unroll
-            for (int c = 0; c < rr; ++c)
-                if (c < NB) s = fma(-pan[c * PM + rr], x[c], s);
-            x[rr] = (rr < nb && jc < nb) ? s : 0.0;
-        }
-#pragma unroll
-        for (int rr = 0; rr < 16; ++rr) il[rr * 16 + jc] = x[rr];
-    }
-}
-
-// A22 (mt x nt, row-major in global memory, leading dimension M) -= L21
-// (LDS panel rows nb.., column-major pitch PM) * U12 (LDS rows, pitch UM,
-// columns uc0..), one 32 x (16*CT) tile at (tr, tc): load, multiply, store.
-template <int CT>
-__device__ __forceinline__ void lu_tile_load(const double* a22, int M, int mt, int nt, int tr, int tc, int lane,
-                                             v4d (&acc)[2][CT]) {
-#pragma unroll
-    for (int x = 0; x < 2; ++x)
-#pragma unroll
-        for (int y = 0; y < CT; ++y) {
-            const int col = tc + 16 * y + (lane & 15);
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int row = tr + 16 * x + (lane >> 4) + 4 * v;
-                acc[x][y][v] = (row < mt && col < nt) ? a22[(size_t)row * M + col] : 0.0;
-            }
-        }
-}
-
-template <int NB, int CT>
-__device__ __forceinline__ void lu_tile_mul(int mt, int nt, int tr, int tc, const double* pan, int PM, int nb,
-                                            const double* us, int UM, int uc0, int lane, v4d (&acc)[2][CT]) {
-#pragma unroll
-    for (int kk = 0; kk < NB / 4; ++kk) {
-        const int kr = kk * 4 + (lane >> 4);
-        double av[2], bw[CT];
-#pragma unroll
-        for (int x = 0; x < 2; ++x) {
-            const int row = tr + 16 * x + (lane & 15);
-            av[x] = (kr < nb && row < mt) ? -pan[kr * PM + nb + row] : 0.0;
-        }
-#pragma unroll
-        for (int y = 0; y < CT; ++y) {
-            const int col = tc + 16 * y + (lane & 15);
-            bw[y] = (kr < nb && col < nt) ? us[kr * UM + uc0 + col] : 0.0;
-        }
-#pragma unroll
-        for (int x = 0; x < 2; ++x)
-#pragma unroll
-            for (int y = 0; y < CT; ++y) acc[x][y] = mfma4(av[x], bw[y], acc[x][y]);
-    }
-}
-
-template <int CT>
-__device__ __forceinline__ void lu_tile_store(double* a22, int M, int mt, int nt, int tr, int tc, int lane,
-                                              const v4d (&acc)[2][CT]) {
-#pragma unroll
-    for (int x = 0; x < 2; ++x)
-#pragma unroll
-        for (int y = 0; y < CT; ++y) {
-            const int col = tc + 16 * y + (lane & 15);
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int row = tr + 16 * x + (lane >> 4) + 4 * v;
-                if (row < mt && col < nt) a22[(size_t)row * M + col] = acc[x][y][v];
-            }
-        }
-}
-
-template <int RPL, int NB, int LU_THREADS>
-__global__ __launch_bounds__(LU_THREADS) void k_getrf(const KArgs ka) {
+template <int NT, int NB>
+__global__ __launch_bounds__(NT) void k_getrf(const KArgs ka) {
+    constexpr int NW = NT / 64;
+    constexpr int KS = NB / 4;   // MFMA k-steps per panel
     const Level& L = ka.L;
-    const int k = ka.c0 + blockIdx.x, t = ka.step;
-    const int r0 = chunk_first(L, k), e = chunk_last(L, k);
+    const int kch = ka.c0 + blockIdx.x, t = ka.step;
+    const int r0 = chunk_first(L, kch), e = chunk_last(L, kch);
     if (t > e - r0) return;
     const int i = r0 + t;
     const int M = L.M;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    constexpr int NW = LU_THREADS / 64;
-    double* a = L.LU + (size_t)i * M * M;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4;
+    double* a = L.Dw + (size_t)kch * M * M;      // working copy, rows in place
+    double* out = L.LU + (size_t)i * M * M;      // factors, rows in pivot order
     extern __shared__ double sm_raw[];
     char* smc = (char*)sm_raw;
-    const GetrfLds lay = getrf_lds_layout(M, NB);
-    const int PM = lay.PM, UM = lay.UM;
-    double* pan0 = (double*)(smc + lay.pan);
-    double* ta = (double*)(smc + lay.us);
-    double* il = (double*)(smc + lay.il);
-    double* rowbuf = (double*)(smc + lay.rowbuf);
+    const LuLds lay = lu_lds_layout(M, NT, NB);
+    const int LP = lay.LP, UP = lay.UP, TP = lay.TP;
+    double* Lb = (double*)(smc + lay.lb);
+    double* Ub = (double*)(smc + lay.ub);
+    double* Tb = (double*)(smc + lay.tb);
+    double* cval = (double*)(smc + lay.cval);
+    double* crow = (double*)(smc + lay.crow);
+    int* cidx = (int*)(smc + lay.cidx);
+    int* piv = (int*)(smc + lay.piv);
     int* list = (int*)(smc + lay.list);
-    int* srcmap = (int*)(smc + lay.srcmap);
-    int* naff_s = (int*)(smc + lay.naff);
-    int* sperm = (int*)(smc + lay.sperm);
+    int* wcnt = (int*)(smc + lay.wcnt);
 
-    for (int rr = tid; rr < M; rr += LU_THREADS) sperm[rr] = rr;
-    int fail_code = 0, fail_col = -1;
-    __syncthreads();
-    PHASE_MARK(t_start);
+    const int row = tid;
+    bool act = row < M;
+    int mypos = -1;
+    int fail_code = 0, fail_col = -1;   // identical in every thread
     const int npan = (M + NB - 1) / NB;
-    // iteration pidx: B and C of panel pidx, overlapped with A of panel pidx+1
-    for (int pidx = -1; pidx < npan; ++pidx) {
-        const int j0 = pidx * NB, nb = min(NB, M - j0), h = M - j0;
-        double* pan = pan0 + (size_t)(pidx & 1) * NB * PM;
-        const int nt = M - j0 - nb, mt = h - nb;
-        const int nb2 = min(NB, nt);
-        double* us = ta + (pidx >= 0 ? j0 + nb : 0);  // U12: rows of ta right of the panel
-        if (pidx >= 0) {
-            PHASE_MARK(t_b0);
-            // ---------------- B: interchanges outside the panel.  Rows j0..j0+nb-1 of
-            // every other column go through LDS (ta, pitch M); displaced rows are
-            // copied after all their sources are read; the L part (left columns)
-            // is written back, the right part stays in ta for U12.
-            const int naff = naff_s[0];
-            for (int c2 = tid; c2 < M - nb; c2 += LU_THREADS) {
-                const int col = c2 < j0 ? c2 : c2 + nb;
-                double top[NB];
+    for (int p = 0; p < npan; ++p) {
+        const int j0 = p * NB, nb = min(NB, M - j0);
+        PHASE_MARK(t_p0);
+        double v[NB];
+        const bool act0 = act;
 #pragma unroll
-                for (int jj = 0; jj < NB; ++jj) top[jj] = jj < nb ? a[(size_t)(j0 + srcmap[jj]) * M + col] : 0.0;
+        for (int c = 0; c < NB; ++c) v[c] = (act && c < nb) ? a[(size_t)row * M + j0 + c] : 0.0;
+
+        // ---------------- panel
 #pragma unroll
-                for (int jj = 0; jj < NB; ++jj)
-                    if (jj < nb) ta[jj * M + col] = top[jj];
-                if (naff > 0) {
-                    double v[NB];
+        for (int jj = 0; jj < NB; ++jj) {
+            if (jj < nb) {
+                const int par = jj & 1;
+                const double x = act ? (isfinite(v[jj]) ? fabs(v[jj]) : __builtin_inf()) : -1.0;
+                const double wm = wave_max(x);
+                const unsigned long long hit = __ballot(x == wm);
+                const int wl = __ffsll((unsigned long long)hit) - 1;
+                if (lane == wl) {
+                    cval[par * NW + w] = wm;
+                    cidx[par * NW + w] = row;
+                    double* cr = crow + (size_t)(par * NW + w) * NB;
 #pragma unroll
-                    for (int q = 0; q < NB; ++q)
-                        if (q < naff) v[q] = a[(size_t)(j0 + list[2 * q + 1]) * M + col];
-#pragma unroll
-                    for (int q = 0; q < NB; ++q)
-                        if (q < naff) a[(size_t)(j0 + list[2 * q]) * M + col] = v[q];
+                    for (int c = jj; c < NB; ++c) cr[c] = v[c];
                 }
-                if (col < j0) {
+                __syncthreads();
+                double best = cval[par * NW];
+                int bw = 0;
 #pragma unroll
-                    for (int jj = 0; jj < NB; ++jj)
-                        if (jj < nb) a[(size_t)(j0 + jj) * M + col] = ta[jj * M + col];
+                for (int q = 1; q < NW; ++q) {
+                    const double cv = cval[par * NW + q];
+                    if (cv > best) { best = cv; bw = q; }
+                }
+                const int prow = cidx[par * NW + bw];
+                const double* pr = crow + (size_t)(par * NW + bw) * NB;
+                const double pv = pr[jj];
+                const bool bad = !isfinite(pv) || pv == 0.0;
+                if (bad && fail_code == 0) {
+                    fail_code = isfinite(pv) ? BTD_ERR_SINGULAR_ : BTD_ERR_NONFINITE_;
+                    fail_col = j0 + jj;
+                }
+                const double rp = bad ? 0.0 : 1.0 / pv;
+                if (row == prow) { act = false; mypos = j0 + jj; }
+                if (tid == 0) piv[jj] = prow;
+                if (act) {
+                    const double l = v[jj] * rp;
+                    v[jj] = l;
+#pragma unroll
+                    for (int c = jj + 1; c < NB; ++c) v[c] = fma(-l, pr[c], v[c]);
                 }
             }
+        }
+        PHASE_MARK(t_p1);
+        PHASE_ADD(0, t_p0, t_p1);
+        // the panel, factored, to the multiplier rows; the multipliers of the
+        // rows not chosen yet also to the working copy
+        if (act0) {
+#pragma unroll
+            for (int c = 0; c < NB; ++c) {
+                if (act && c < nb) a[(size_t)row * M + j0 + c] = v[c];
+                Lb[row * LP + c] = v[c];
+            }
+        }
+        // the rows not chosen yet, listed in row order
+        {
+            const unsigned long long am = __ballot(act);
+            if (lane == 0) wcnt[w] = __popcll(am);
             __syncthreads();
-            // U12 = inv(L11) A12 on MFMA, in place in us, and to global memory
-            for (int tcol = w * 16; tcol < nt; tcol += NW * 16) {
-                v4d acc = {0.0, 0.0, 0.0, 0.0};
-                const int col = tcol + (lane & 15);
+            int base = 0;
 #pragma unroll
-                for (int kk = 0; kk < NB / 4; ++kk) {
-                    const int kr = kk * 4 + (lane >> 4);
-                    const double bw = col < nt ? us[kr * UM + col] : 0.0;
-                    acc = mfma4(il[(lane & 15) * 16 + kr], bw, acc);
-                }
+            for (int q = 0; q < NW; ++q) base += q < w ? wcnt[q] : 0;
+            if (act) list[base + __popcll(am & ((1ull << lane) - 1ull))] = row;
+        }
+        const int w2 = M - j0 - nb;   // columns right of the panel (0 only after the last panel)
+        if (w2 > 0) {
+        // ---------------- inv(L11): two 16 x 16 diagonal blocks by forward
+        // substitution (lanes 0..15 the first, 16..31 the second), then the
+        // off-diagonal block -inv(L_22) L_21 inv(L_11) on MFMA.
+        if (w == 0 && lane < NB) {
+            const int half = lane / 16, jc = lane % 16, o = half * 16;
+            double x[16];
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int row = (lane >> 4) + 4 * v;
-                    if (row < nb && col < nt) {
-                        us[row * UM + col] = acc[v];
-                        a[(size_t)(j0 + row) * M + j0 + nb + col] = acc[v];
+            for (int rr = 0; rr < 16; ++rr) {
+                double s = (rr == jc) ? 1.0 : 0.0;
+                const double* lr = Lb + piv[o + rr] * LP + o;
+#pragma unroll
+                for (int c = 0; c < rr; ++c) s = fma(-lr[c], x[c], s);
+                x[rr] = rr >= jc ? s : 0.0;
+            }
+#pragma unroll
+            for (int rr = 0; rr < 16; ++rr) Tb[(o + rr) * TP + o + jc] = x[rr];
+            if (NB == 32) {
+#pragma unroll
+                for (int rr = 0; rr < 16; ++rr) Tb[rr * TP + 16 + jc] = 0.0;
+            }
+        }
+        __syncthreads();
+        if (NB == 32 && w == 0) {
+            // W = L_21 inv(L_11) (16 x 16), then T_21 = -inv(L_22) W
+            v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk)
+                acc = mfma4(Lb[piv[16 + (lane & 15)] * LP + 4 * kk + g], Tb[(4 * kk + g) * TP + (lane & 15)], acc);
+            double* wt = crow;   // 16 x 16 scratch (the candidate slots are free here)
+#pragma unroll
+            for (int vv = 0; vv < 4; ++vv) wt[(g + 4 * vv) * 16 + (lane & 15)] = acc[vv];
+            wave_lds_sync();
+            v4d acc2 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk)
+                acc2 = mfma4(-Tb[(16 + (lane & 15)) * TP + 16 + 4 * kk + g], wt[(4 * kk + g) * 16 + (lane & 15)], acc2);
+#pragma unroll
+            for (int vv = 0; vv < 4; ++vv) Tb[(16 + g + 4 * vv) * TP + (lane & 15)] = acc2[vv];
+        }
+        __syncthreads();
+        // ---------------- U12 = inv(L11) A12, 16-column strips over the waves,
+        // every strip's A12 operands loaded before the first product
+        {
+            constexpr int SPW = (NT - NB + 16 * NW - 1) / (16 * NW);   // strips per wave at most
+            double bop[SPW][KS];
+#pragma unroll
+            for (int sidx = 0; sidx < SPW; ++sidx) {
+                const int col = (w + sidx * NW) * 16 + (lane & 15);
+#pragma unroll
+                for (int kk = 0; kk < KS; ++kk)
+                    bop[sidx][kk] = col < w2 ? a[(size_t)piv[4 * kk + g] * M + j0 + nb + col] : 0.0;
+            }
+#pragma unroll
+            for (int sidx = 0; sidx < SPW; ++sidx) {
+                const int cs = (w + sidx * NW) * 16;
+                if (cs < w2) {
+                    const int col = cs + (lane & 15);
+#pragma unroll
+                    for (int x = 0; x < NB / 16; ++x) {
+                        v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                        for (int kk = 0; kk < KS; ++kk)
+                            acc = mfma4(Tb[(16 * x + (lane & 15)) * TP + 4 * kk + g], bop[sidx][kk], acc);
+#pragma unroll
+                        for (int vv = 0; vv < 4; ++vv) Ub[(16 * x + g + 4 * vv) * UP + col] = acc[vv];
                     }
                 }
             }
-            __syncthreads();
-            PHASE_MARK(t_c0);
-            PHASE_ADD(1, t_b0, t_c0);
-            // ---------------- C (first part): the columns of panel pidx+1, all waves
-            if (mt > 0) {
-                double* a22 = a + (size_t)(j0 + nb) * M + j0 + nb;
-                for (int tr = w * 32; tr < mt; tr += NW * 32) {
-                    v4d acc[2][1];
-                    lu_tile_load<1>(a22, M, mt, nb2, tr, 0, lane, acc);
-                    lu_tile_mul<NB, 1>(mt, nb2, tr, 0, pan, PM, nb, us, UM, 0, lane, acc);
-                    lu_tile_store<1>(a22, M, mt, nb2, tr, 0, lane, acc);
+        }
+        __syncthreads();
+        }
+        PHASE_MARK(t_p2);
+        PHASE_ADD(1, t_p1, t_p2);
+        // ---------------- the panel's pivot rows, final, in pivot order: one
+        // wave per row, all loads before the stores
+        {
+            constexpr int RW = (NB + NW - 1) / NW, CL = NT / 64;
+            double val[RW][CL];
+#pragma unroll
+            for (int q = 0; q < RW; ++q) {
+                const int rr = w + q * NW;
+                const int pr = rr < nb ? piv[rr] : 0;
+#pragma unroll
+                for (int u = 0; u < CL; ++u) {
+                    const int c = lane + 64 * u;
+                    double x = 0.0;
+                    if (rr < nb && c < M) {
+                        if (c < j0) x = a[(size_t)pr * M + c];
+                        else if (c < j0 + nb) x = Lb[pr * LP + c - j0];
+                        else x = Ub[rr * UP + c - j0 - nb];
+                    }
+                    val[q][u] = x;
                 }
             }
-            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < RW; ++q) {
+                const int rr = w + q * NW;
+#pragma unroll
+                for (int u = 0; u < CL; ++u) {
+                    const int c = lane + 64 * u;
+                    if (rr < nb && c < M) out[(size_t)(j0 + rr) * M + c] = val[q][u];
+                }
+            }
         }
-        if (pidx + 1 >= npan) break;
-        PHASE_MARK(t_a0);
-        if (w == 0) {
-            // ---------------- A: panel pidx+1
-            double* pan_next = pan0 + (size_t)((pidx + 1) & 1) * NB * PM;
-            lu_panel<RPL, NB>(a, M, (pidx + 1) * NB, PM, pan_next, il, rowbuf, list, srcmap, naff_s, sperm, lane,
-                              fail_code, fail_col);
-            PHASE_MARK(t_a1);
-            PHASE_ADD(0, t_a0, t_a1);
-        } else if (pidx >= 0 && mt > 0) {
-            // ---------------- C (rest) of panel pidx: 32 x 32 tiles over waves 1..NW-1,
-            // the next tile's A22 loaded before the current one is multiplied
-            double* a22r = a + (size_t)(j0 + nb) * M + j0 + nb + nb2;
-            const int ntr = nt - nb2;
-            const int t32r = (mt + 31) / 32, t32c = (ntr + 31) / 32, ntiles = t32r * t32c;
-            v4d cur[2][2], nxt[2][2];
-            int tile = w - 1;
-            if (tile < ntiles) lu_tile_load<2>(a22r, M, mt, ntr, (tile / t32c) * 32, (tile % t32c) * 32, lane, cur);
-            while (tile < ntiles) {
-                const int tnext = tile + NW - 1;
-                if (tnext < ntiles)
-                    lu_tile_load<2>(a22r, M, mt, ntr, (tnext / t32c) * 32, (tnext % t32c) * 32, lane, nxt);
-                const int tr = (tile / t32c) * 32, tc = (tile % t32c) * 32;
-                lu_tile_mul<NB, 2>(mt, ntr, tr, tc, pan, PM, nb, us, UM, nb2, lane, cur);
-                lu_tile_store<2>(a22r, M, mt, ntr, tr, tc, lane, cur);
+        PHASE_MARK(t_p3);
+        PHASE_ADD(2, t_p2, t_p3);
+        if (w2 <= 0) break;
+        PHASE_MARK(t_p4);
+        // ---------------- A22 -= L21 U12, 32 x 32 tiles, the next tile of the
+        // wave loaded before the current one is multiplied
+        {
+            const int h2 = w2;   // rows not chosen yet
+            const int tc_n = (w2 + 31) / 32, ntiles = ((h2 + 31) / 32) * tc_n;
+            double* a2 = a + j0 + nb;
+            auto load_tile = [&](int tile, v4d (&c)[2][2], int (&crw)[2][4]) {
+                const int tr = (tile / tc_n) * 32, tc = (tile % tc_n) * 32;
 #pragma unroll
                 for (int x = 0; x < 2; ++x)
 #pragma unroll
+                    for (int vv = 0; vv < 4; ++vv) {
+                        const int idx = tr + 16 * x + g + 4 * vv;
+                        crw[x][vv] = idx < h2 ? list[idx] : -1;
+                    }
+#pragma unroll
+                for (int x = 0; x < 2; ++x)
+#pragma unroll
+                    for (int y = 0; y < 2; ++y) {
+                        const int col = tc + 16 * y + (lane & 15);
+#pragma unroll
+                        for (int vv = 0; vv < 4; ++vv)
+                            c[x][y][vv] = (crw[x][vv] >= 0 && col < w2) ? a2[(size_t)crw[x][vv] * M + col] : 0.0;
+                    }
+            };
+            v4d cur[2][2], nxt[2][2];
+            int crw[2][4], nrw[2][4];
+            int tile = w;
+            if (tile < ntiles) load_tile(tile, cur, crw);
+            while (tile < ntiles) {
+                const int tnext = tile + NW;
+                if (tnext < ntiles) load_tile(tnext, nxt, nrw);
+                const int tr = (tile / tc_n) * 32, tc = (tile % tc_n) * 32;
+                int arw[2];
+#pragma unroll
+                for (int x = 0; x < 2; ++x) {
+                    const int idx = tr + 16 * x + (lane & 15);
+                    arw[x] = idx < h2 ? list[idx] : -1;
+                }
+#pragma unroll
+                for (int kk = 0; kk < KS; ++kk) {
+                    double av[2], bv[2];
+#pragma unroll
+                    for (int x = 0; x < 2; ++x) av[x] = arw[x] >= 0 ? -Lb[arw[x] * LP + 4 * kk + g] : 0.0;
+#pragma unroll
+                    for (int y = 0; y < 2; ++y) {
+                        const int col = tc + 16 * y + (lane & 15);
+                        bv[y] = col < w2 ? Ub[(4 * kk + g) * UP + col] : 0.0;
+                    }
+#pragma unroll
+                    for (int x = 0; x < 2; ++x)
+#pragma unroll
+                        for (int y = 0; y < 2; ++y) cur[x][y] = mfma4(av[x], bv[y], cur[x][y]);
+                }
+#pragma unroll
+                for (int x = 0; x < 2; ++x)
+#pragma unroll
+                    for (int y = 0; y < 2; ++y) {
+                        const int col = tc + 16 * y + (lane & 15);
+#pragma unroll
+                        for (int vv = 0; vv < 4; ++vv)
+                            if (crw[x][vv] >= 0 && col < w2) a2[(size_t)crw[x][vv] * M + col] = cur[x][y][vv];
+                    }
+#pragma unroll
+                for (int x = 0; x < 2; ++x) {
+#pragma unroll
                     for (int y = 0; y < 2; ++y) cur[x][y] = nxt[x][y];
+#pragma unroll
+                    for (int vv = 0; vv < 4; ++vv) crw[x][vv] = nrw[x][vv];
+                }
                 tile = tnext;
             }
         }
         __syncthreads();
+        PHASE_MARK(t_p5);
+        PHASE_ADD(4, t_p4, t_p5);
     }
-    PHASE_MARK(t_end);
-    PHASE_ADD(2, t_start, t_end);
     int* perm = L.perm + (size_t)i * M;
-    for (int rr = tid; rr < M; rr += LU_THREADS) perm[rr] = sperm[rr];
-    if (lane == 0 && w == 0 && fail_code != 0) report_status(ka.status, L.level, i, fail_col, fail_code);
+    if (mypos >= 0) perm[mypos] = row;
+    if (tid == 0 && fail_code != 0) report_status(ka.status, L.level, i, fail_col, fail_code);
 }
 
 // Preparation of the factors of every D_i factored at this step for the
@@ -1355,25 +1319,21 @@ hipError_t launch_couple(const KArgs& ka, hipStream_t s) { return launch_gemm<GM
 hipError_t launch_couple_rhs(const KArgs& ka, hipStream_t s) { return launch_gemm<GM_COUPLE_RHS, 1>(ka, ka.L.P - 1, ka.L.M, ka.R, s); }
 hipError_t launch_recover(const KArgs& ka, hipStream_t s) { return launch_gemm<GM_RECOVER, 1>(ka, ka.L.N, ka.L.M, ka.R, s); }
 
-static int getrf_rpl(int M) { return M <= 64 ? 1 : M <= 128 ? 2 : M <= 256 ? 4 : 8; }
-#ifndef BTD_GETRF_NB
-#define BTD_GETRF_NB 16
-#endif
-static int getrf_nb(int M) { return M <= 256 ? BTD_GETRF_NB : 8; }
+// One thread per row: 256 threads and 32-column panels up to M = 256,
+// 512 threads and 16-column panels above (the LDS holds the multiplier rows
+// and U12 of one panel).
+static bool getrf_small(int M) { return M <= 256; }
 
-size_t getrf_lds_bytes(int M) { return getrf_lds_layout(M, getrf_nb(M)).total; }
+size_t getrf_lds_bytes(int M) {
+    return getrf_small(M) ? lu_lds_layout(M, 256, 32).total : lu_lds_layout(M, 512, 16).total;
+}
 
 hipError_t launch_getrf(const KArgs& ka, hipStream_t s) {
     const int M = ka.L.M;
     const size_t lds = getrf_lds_bytes(M);
     dim3 grid(ka.nc);
-    // 4 waves: the register panel of wave 0 needs more than the 256 registers per wave of an 8-wave group
-    switch (getrf_rpl(M)) {
-        case 1: hipLaunchKernelGGL((k_getrf<1, BTD_GETRF_NB, 256>), grid, dim3(256), lds, s, ka); break;
-        case 2: hipLaunchKernelGGL((k_getrf<2, BTD_GETRF_NB, 256>), grid, dim3(256), lds, s, ka); break;
-        case 4: hipLaunchKernelGGL((k_getrf<4, BTD_GETRF_NB, 256>), grid, dim3(256), lds, s, ka); break;
-        default: hipLaunchKernelGGL((k_getrf<8, 8, 256>), grid, dim3(256), lds, s, ka); break;
-    }
+    if (getrf_small(M)) hipLaunchKernelGGL((k_getrf<256, 32>), grid, dim3(256), lds, s, ka);
+    else hipLaunchKernelGGL((k_getrf<512, 16>), grid, dim3(512), lds, s, ka);
     return hipGetLastError();
 }
 
@@ -1470,8 +1430,7 @@ hipError_t read_phase_times(unsigned long long* out) {
 hipError_t configure_kernels() {
     const int lds_max = 160 * 1024;
     hipError_t err;
-    const void* getrf_kernels[] = {(const void*)k_getrf<1, BTD_GETRF_NB, 256>, (const void*)k_getrf<2, BTD_GETRF_NB, 256>,
-                                   (const void*)k_getrf<4, BTD_GETRF_NB, 256>, (const void*)k_getrf<8, 8, 256>};
+    const void* getrf_kernels[] = {(const void*)k_getrf<256, 32>, (const void*)k_getrf<512, 16>};
     for (const void* f : getrf_kernels) {
         err = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
         if (err != hipSuccess) return err;

@@ -5,6 +5,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -23,7 +24,7 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 struct LevelPlan {
     int N = 0, M = 0, P = 1, nmax = 0;
     std::vector<int> sep;  // P+1 entries: -1, q_0 .. q_{P-2}, N
-    size_t off_LU = 0, off_DI = 0, off_W = 0, off_Z = 0, off_Hd = 0, off_Hb = 0, off_Hc = 0;
+    size_t off_LU = 0, off_Dw = 0, off_DI = 0, off_W = 0, off_Z = 0, off_Hd = 0, off_Hb = 0, off_Hc = 0;
     size_t off_perm = 0, off_sep = 0;
 };
 
@@ -96,6 +97,7 @@ size_t build_levels(const btd_desc_t* d, std::vector<LevelPlan>& lv) {
             if (nk > L.nmax) L.nmax = nk;
         }
         L.off_LU = off; off = align_up(off + sizeof(double) * N * MM);
+        L.off_Dw = off; off = align_up(off + sizeof(double) * P * MM);
         L.off_DI = off; off = align_up(off + sizeof(double) * N * nblk * 2048);
         L.off_W = off; off = align_up(off + sizeof(double) * N * MM * 2);
         if (P > 1) {
@@ -154,10 +156,19 @@ StreamPool* stream_pool() {
     return &p;
 }
 
-// Groups for a level of P chunks: at least 8 chunks per group.
+// Groups for a level of P chunks: at least 8 chunks per group, at most
+// BTD_STREAM_GROUPS (environment, 1..4; default 1: one stream, measured
+// faster on MI355X than concurrent groups once every chunk's step fills
+// the GPU by itself).
 int chunk_groups(int P) {
+    static int cap = -1;
+    if (cap < 0) {
+        const char* env = std::getenv("BTD_STREAM_GROUPS");
+        const int v = env ? std::atoi(env) : 0;
+        cap = (v >= 1 && v <= kMaxGroups) ? v : 1;
+    }
     int g = P / 8;
-    return g < 1 ? 1 : (g > kMaxGroups ? kMaxGroups : g);
+    return g < 1 ? 1 : (g > cap ? cap : g);
 }
 
 // Event pairs around the launches of one kernel class (measurement only).
@@ -200,6 +211,7 @@ struct btd_plan_s {
             d.C = (const double*)(ws + up.off_Hc);
         }
         d.LU = (double*)(ws + L.off_LU);
+        d.Dw = (double*)(ws + L.off_Dw);
         d.DI = (double*)(ws + L.off_DI);
         d.W = (double*)(ws + L.off_W);
         d.Z = L.P > 1 ? (double*)(ws + L.off_Z) : nullptr;
