@@ -1038,6 +1038,195 @@ __global__ __launch_bounds__(256) void k_getrs(const KArgs ka) {
                         ownb);
 }
 
+// ------------------------------------------------------------------ triangular solves, one wave per slab
+//
+// For M <= 256: X := U^{-1} L^{-1} (P X) on a slab of 16*NT16 columns of
+// W_i, held entirely in one wave's MFMA accumulators; no LDS and no
+// barrier.  With the scaled off-diagonal blocks of k_diag_prep a sweep
+// subtracts Lt_{b',b} w_b (forward, b' > b) or Ut_{b',b} w_b (backward,
+// b' < b) with the unsolved block w_b, and the diagonal inverses are applied
+// to all blocks after each sweep.
+//
+// Register layout: in lane l (g = l >> 4, j = l & 15) accumulator register
+// v of row tile tr of block b holds row 32b + 8g + 4tr + v, column j of
+// the column tile.  Then the block product's contraction can run with lane
+// group g taking k = 8g + kk at MFMA step kk (kk = 0..7): the right operand
+// of step kk is this lane's own register (tile kk >> 2, register kk & 3),
+// and the left operand (a block of the factors) is read as eight
+// consecutive doubles per lane.  For output tile tr the left operand of
+// lane l is row 8(i & 3) + 4tr + (i >> 2), i = l & 15, of the block.
+template <int NBLK>
+__host__ __device__ constexpr int trsm_npairs() { return NBLK * (NBLK - 1) / 2; }
+
+// p-th (source, target) block pair: forward sweep b = 0.., b' = b+1..;
+// backward sweep b = NBLK-1..1, b' = 0..b-1.
+template <int NBLK>
+__host__ __device__ constexpr int trsm_pair(int p, bool fwd, bool want_src) {
+    int q = 0;
+    for (int s = 0; s < NBLK; ++s) {
+        const int b = fwd ? s : NBLK - 1 - s;
+        const int lo = fwd ? b + 1 : 0, hi = fwd ? NBLK : b;
+        for (int bp = lo; bp < hi; ++bp) {
+            if (q == p) return want_src ? b : bp;
+            ++q;
+        }
+    }
+    return 0;
+}
+
+// Left operand: rows of block bp (permuted per output tile), columns
+// 32 b + 8 g .. + 7, scaled by sgn; zero outside the matrix.
+__device__ __forceinline__ void trsmw_load(const double* __restrict__ src, int ld, int M, int bp, int b, int lane,
+                                           double sgn, double (&o)[2][8]) {
+    const int g = lane >> 4, i16 = lane & 15;
+    const int c0 = b * DB + g * 8;
+#pragma unroll
+    for (int tr = 0; tr < 2; ++tr) {
+        const int row = bp * DB + 8 * (i16 & 3) + 4 * tr + (i16 >> 2);
+        if (row < M && c0 + 7 < M && (ld & 3) == 0) {
+            const double4* p4 = (const double4*)(src + (size_t)row * ld + c0);
+            const double4 v0 = p4[0], v1 = p4[1];
+            o[tr][0] = sgn * v0.x; o[tr][1] = sgn * v0.y; o[tr][2] = sgn * v0.z; o[tr][3] = sgn * v0.w;
+            o[tr][4] = sgn * v1.x; o[tr][5] = sgn * v1.y; o[tr][6] = sgn * v1.z; o[tr][7] = sgn * v1.w;
+        } else {
+#pragma unroll
+            for (int kk = 0; kk < 8; ++kk)
+                o[tr][kk] = (row < M && c0 + kk < M) ? sgn * src[(size_t)row * ld + c0 + kk] : 0.0;
+        }
+    }
+}
+
+// x_bp -= T_{bp,b} x_b (the operand already negated)
+template <int NBLK, int NT16, int B, int BP>
+__device__ __forceinline__ void trsmw_update(v4d (&x)[NBLK][2][NT16], const double (&o)[2][8]) {
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk)
+#pragma unroll
+        for (int tr = 0; tr < 2; ++tr)
+#pragma unroll
+            for (int nt = 0; nt < NT16; ++nt)
+                x[BP][tr][nt] = mfma4(o[tr][kk], x[B][kk >> 2][nt][kk & 3], x[BP][tr][nt]);
+}
+
+// One sweep over the block pairs from P on, operands one pair ahead.
+template <int NBLK, int NT16, bool FWD, int P>
+__device__ __forceinline__ void trsmw_sweep(v4d (&x)[NBLK][2][NT16], const double* __restrict__ lu, int M, int lane,
+                                            double (&cur)[2][8], double (&nxt)[2][8]) {
+    constexpr int NP = trsm_npairs<NBLK>();
+    if constexpr (P < NP) {
+        constexpr int B = trsm_pair<NBLK>(P, FWD, true), BP = trsm_pair<NBLK>(P, FWD, false);
+        if constexpr (P + 1 < NP)
+            trsmw_load(lu, M, M, trsm_pair<NBLK>(P + 1, FWD, false), trsm_pair<NBLK>(P + 1, FWD, true), lane, -1.0,
+                       nxt);
+        trsmw_update<NBLK, NT16, B, BP>(x, cur);
+        trsmw_sweep<NBLK, NT16, FWD, P + 1>(x, lu, M, lane, nxt, cur);
+    }
+}
+
+// x_b := inv(T_bb) x_b for every block, the next block's inverse loaded
+// ahead (zero past the last block, whose x is zero).
+template <int NBLK, int NT16, int B>
+__device__ __forceinline__ void trsmw_diag(v4d (&x)[NBLK][2][NT16], const double* __restrict__ di, int nblk, int dir,
+                                           int lane, double (&cur)[2][8], double (&nxt)[2][8]) {
+    if constexpr (B < NBLK) {
+        if constexpr (B + 1 < NBLK)
+            trsmw_load(di + (size_t)(B + 1 < nblk ? B + 1 : 0) * DI_STRIDE + (dir ? DB * DB : 0), DB,
+                       B + 1 < nblk ? DB : 0, 0, 0, lane, 1.0, nxt);
+        v4d nw[2][NT16];
+#pragma unroll
+        for (int tr = 0; tr < 2; ++tr)
+#pragma unroll
+            for (int nt = 0; nt < NT16; ++nt) nw[tr][nt] = (v4d){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kk = 0; kk < 8; ++kk)
+#pragma unroll
+            for (int tr = 0; tr < 2; ++tr)
+#pragma unroll
+                for (int nt = 0; nt < NT16; ++nt) nw[tr][nt] = mfma4(cur[tr][kk], x[B][kk >> 2][nt][kk & 3], nw[tr][nt]);
+#pragma unroll
+        for (int tr = 0; tr < 2; ++tr)
+#pragma unroll
+            for (int nt = 0; nt < NT16; ++nt) x[B][tr][nt] = nw[tr][nt];
+        trsmw_diag<NBLK, NT16, B + 1>(x, di, nblk, dir, lane, nxt, cur);
+    }
+}
+
+// RHS = W_i = [C_i | -B_i Y_{i-1}] of the chunk's row at step t; grid =
+// nslab slabs x chunks in one dimension, one wave each, XCD-aware order so
+// that the slabs of one chunk share an L2.
+template <int NBLK, int NT16>
+__global__ __launch_bounds__(64) void k_getrs_w(const KArgs ka, int nslab) {
+    const Level& L = ka.L;
+    const int M = L.M;
+    const int lid = xcd_logical_id(blockIdx.x, gridDim.x);
+    const int k = ka.c0 + lid / nslab, slab = lid % nslab;
+    const int r = chunk_first(L, k), e = chunk_last(L, k), t = ka.step;
+    if (t > e - r) return;
+    const int i = r + t;
+    constexpr int SW = 16 * NT16;
+    const int c0 = slab * SW;
+    const int e_hi = (i != L.N - 1) ? M : 0;          // E_i columns [0, e_hi)
+    const int y_hi = (k > 0) ? 2 * M : M;             // Y_i columns [M, y_hi)
+    if (!(c0 < e_hi || (c0 < y_hi && c0 + SW > M))) return;
+    const int lane = threadIdx.x, g = lane >> 4, j = lane & 15;
+    const int nblk = (M + DB - 1) / DB;
+    const double* lu = L.LU + (size_t)i * M * M;
+    const double* di = L.DI + (size_t)i * nblk * DI_STRIDE;
+    const int* perm = L.perm + (size_t)i * M;
+    double* X = L.W + (size_t)i * M * 2 * M;
+    const int ld = 2 * M;
+    v4d x[NBLK][2][NT16];
+    int prow[NBLK][2][4];
+#pragma unroll
+    for (int b = 0; b < NBLK; ++b)
+#pragma unroll
+        for (int tr = 0; tr < 2; ++tr)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = b * DB + 8 * g + 4 * tr + v;
+                prow[b][tr][v] = row < M ? perm[row] : -1;
+            }
+#pragma unroll
+    for (int b = 0; b < NBLK; ++b)
+#pragma unroll
+        for (int tr = 0; tr < 2; ++tr)
+#pragma unroll
+            for (int nt = 0; nt < NT16; ++nt) {
+                const int col = c0 + 16 * nt + j;
+                const bool cv = col < e_hi || (col >= M && col < y_hi);
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    x[b][tr][nt][v] = (cv && prow[b][tr][v] >= 0) ? X[(size_t)prow[b][tr][v] * ld + col] : 0.0;
+            }
+    double o0[2][8], o1[2][8];
+    if constexpr (NBLK > 1) {
+        trsmw_load(lu, M, M, trsm_pair<NBLK>(0, true, false), trsm_pair<NBLK>(0, true, true), lane, -1.0, o0);
+        trsmw_sweep<NBLK, NT16, true, 0>(x, lu, M, lane, o0, o1);
+    }
+    trsmw_load(di, DB, DB, 0, 0, lane, 1.0, o0);
+    trsmw_diag<NBLK, NT16, 0>(x, di, nblk, 0, lane, o0, o1);
+    if constexpr (NBLK > 1) {
+        trsmw_load(lu, M, M, trsm_pair<NBLK>(0, false, false), trsm_pair<NBLK>(0, false, true), lane, -1.0, o0);
+        trsmw_sweep<NBLK, NT16, false, 0>(x, lu, M, lane, o0, o1);
+    }
+    trsmw_load(di + DB * DB, DB, DB, 0, 0, lane, 1.0, o0);
+    trsmw_diag<NBLK, NT16, 0>(x, di, nblk, 1, lane, o0, o1);
+#pragma unroll
+    for (int b = 0; b < NBLK; ++b)
+#pragma unroll
+        for (int tr = 0; tr < 2; ++tr)
+#pragma unroll
+            for (int nt = 0; nt < NT16; ++nt) {
+                const int col = c0 + 16 * nt + j;
+                const bool cv = col < e_hi || (col >= M && col < y_hi);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = b * DB + 8 * g + 4 * tr + v;
+                    if (cv && row < M) X[(size_t)row * ld + col] = x[b][tr][nt][v];
+                }
+            }
+}
+
 // ------------------------------------------------------------------ right-hand-side sweeps
 //
 // One workgroup per (chunk, group of RB columns) runs the chunk's whole
@@ -1345,12 +1534,41 @@ hipError_t launch_diag_inv(const KArgs& ka, hipStream_t s) {
 
 static int slab_width(int M) { return M <= 256 ? 32 : 16; }
 
+template <int NBLK, int NT16>
+static void launch_getrs_w(const KArgs& ka, hipStream_t s) {
+    const int nslab = cdiv(2 * ka.L.M, 16 * NT16);
+    hipLaunchKernelGGL((k_getrs_w<NBLK, NT16>), dim3(nslab * ka.nc), dim3(64), 0, s, ka, nslab);
+}
+
+// M <= 256: one wave per slab, the widest slab (most reuse of each factor
+// operand) that still gives every SIMD of the GPU a wave; above: the
+// workgroup slab kernel.
 hipError_t launch_getrs(const KArgs& ka, hipStream_t s) {
-    const int M = ka.L.M, sw = slab_width(M);
+    const int M = ka.L.M;
+    if (M <= 256) {
+        const int nblk = cdiv(M, DB);
+        const int nbp = nblk <= 1 ? 1 : nblk <= 2 ? 2 : nblk <= 4 ? 4 : 8;
+        const int simds = 1024;
+        int nt = 1;
+        for (int c = 4; c >= 2; c /= 2)
+            if (nbp * c <= 16 && ka.nc * cdiv(2 * M, 16 * c) >= simds) { nt = c; break; }
+        switch (nbp * 10 + nt) {
+            case 14: launch_getrs_w<1, 4>(ka, s); break;
+            case 11: case 12: launch_getrs_w<1, 4>(ka, s); break;
+            case 21: launch_getrs_w<2, 1>(ka, s); break;
+            case 22: launch_getrs_w<2, 2>(ka, s); break;
+            case 24: launch_getrs_w<2, 4>(ka, s); break;
+            case 41: launch_getrs_w<4, 1>(ka, s); break;
+            case 42: launch_getrs_w<4, 2>(ka, s); break;
+            case 44: launch_getrs_w<4, 4>(ka, s); break;
+            case 81: launch_getrs_w<8, 1>(ka, s); break;
+            default: launch_getrs_w<8, 2>(ka, s); break;
+        }
+        return hipGetLastError();
+    }
+    const int sw = slab_width(M);
     dim3 grid(cdiv(2 * M, sw) * ka.nc);
-    if (M <= 128) hipLaunchKernelGGL((k_getrs<32, 1>), grid, dim3(256), 0, s, ka);
-    else if (M <= 256) hipLaunchKernelGGL((k_getrs<32, 2>), grid, dim3(256), 0, s, ka);
-    else hipLaunchKernelGGL((k_getrs<16, 4>), grid, dim3(256), 0, s, ka);
+    hipLaunchKernelGGL((k_getrs<16, 4>), grid, dim3(256), 0, s, ka);
     return hipGetLastError();
 }
 
