@@ -88,6 +88,18 @@ __device__ __forceinline__ int wave_min_int(int v) {
                min(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
 }
 
+// Maximum of an unsigned 32-bit value over the 64 lanes, uniform result:
+// one DPP-modified v_max_u32 per stage.
+__device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xf, 0xf, false));
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xf, 0xf, false));
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xf, 0xf, false));
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xf, 0xf, false));
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x142, 0xa, 0xf, false));
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x143, 0xc, 0xf, false));
+    return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
+}
+
 // Workgroup copy of n elements with UNR loads in flight per thread before
 // the matching stores (a plain strided loop waits for every load).
 template <int UNR, class LD, class ST>
@@ -416,7 +428,7 @@ __host__ __device__ inline LuLds lu_lds_layout(int M, int NT, int NB) {
     l.lb = off; off += sizeof(double) * (size_t)NT * l.LP;
     l.ub = off; off += sizeof(double) * (size_t)NB * l.UP;
     l.tb = off; off += sizeof(double) * (size_t)NB * l.TP;
-    l.cval = off; off += sizeof(double) * 2 * NW;
+    l.cval = off; off += sizeof(double) * 2 * NW * 4;
     l.crow = off; off += sizeof(double) * 2 * NW * (size_t)NB;
     l.cidx = off; off += sizeof(int) * 2 * NW;
     l.piv = off; off += sizeof(int) * NB;
@@ -424,6 +436,94 @@ __host__ __device__ inline LuLds lu_lds_layout(int M, int NT, int NB) {
     l.wcnt = off; off += sizeof(int) * (NW + 1);
     l.total = (off + 15) & ~(size_t)15;
     return l;
+}
+
+// The column steps of one panel.  Thread t holds the panel row t in v.
+// Pivot search per column: key = bits(|value|) + 1 for rows not chosen yet
+// (non-finite values count as +inf so that they win and are reported),
+// 0 otherwise; its high word is reduced with 32-bit DPP maxima, and only
+// when several lanes share the maximal high word the low word decides among
+// them (lowest lane on exact ties).  The wave's winner publishes its key,
+// the reciprocal of its value (two Newton steps from v_rcp_f64), its row and
+// its value in the next column to a 32-byte slot, and the rest of its row to
+// crow; after the barrier every thread picks the largest key (lowest wave on
+// ties) without a dependent LDS read and eliminates.
+template <int NT, int NB, bool FULL>
+__device__ __forceinline__ void lu_panel_steps(double (&v)[NB], bool& act, int& mypos, int& fail_code, int& fail_col,
+                                               int j0, int nb, int row, int lane, int w, double* cslot, double* crow) {
+    constexpr int NW = NT / 64;
+    constexpr unsigned long long KINF = 0x7FF0000000000001ull;   // key of a non-finite value
+#pragma unroll
+    for (int jj = 0; jj < NB; ++jj) {
+        if (FULL || jj < nb) {
+            PHASE_MARK(t_s0);
+            const int par = jj & 1;
+            const double vj = v[jj];
+            const unsigned long long bits =
+                isfinite(vj) ? (unsigned long long)__double_as_longlong(fabs(vj)) + 1ull : KINF;
+            const unsigned long long key = act ? bits : 0ull;
+            double r = __builtin_amdgcn_rcp(vj);
+            r = fma(r, fma(-vj, r, 1.0), r);
+            r = fma(r, fma(-vj, r, 1.0), r);
+            const unsigned hi = (unsigned)(key >> 32);
+            const unsigned mhi = wave_max_u32(hi);
+            unsigned long long tied = __ballot(hi == mhi);
+            if (__popcll(tied) > 1) {
+                const unsigned lo = hi == mhi ? (unsigned)key : 0u;
+                const unsigned mlo = wave_max_u32(lo);
+                tied = __ballot(hi == mhi && lo == mlo);
+            }
+            const int wl = __ffsll((unsigned long long)tied) - 1;
+            if (lane == wl) {
+                double* sl = cslot + (par * NW + w) * 4;
+                sl[0] = __longlong_as_double((long long)key);
+                sl[1] = r;
+                sl[2] = (double)row;
+                if (jj + 1 < NB) sl[3] = v[jj + 1];
+                double* cr = crow + (size_t)(par * NW + w) * NB;
+#pragma unroll
+                for (int c = jj + 2; c < NB; ++c) cr[c] = v[c];
+            }
+            PHASE_MARK(t_s1);
+            __syncthreads();
+            PHASE_MARK(t_s2);
+            PHASE_ADD(5, t_s0, t_s1);
+            PHASE_ADD(6, t_s1, t_s2);
+            // the four keys first (independent reads), then everything of the
+            // winning wave in one round of reads
+            const unsigned long long* skey = (const unsigned long long*)cslot;
+            unsigned long long kq[NW];
+#pragma unroll
+            for (int q = 0; q < NW; ++q) kq[q] = skey[(par * NW + q) * 4];
+            unsigned long long bk = kq[0];
+            int bw = 0;
+#pragma unroll
+            for (int q = 1; q < NW; ++q) {
+                const bool tk = kq[q] > bk;
+                bk = tk ? kq[q] : bk;
+                bw = tk ? q : bw;
+            }
+            const double* sl = cslot + (par * NW + bw) * 4;
+            const double rcp = sl[1], prw = sl[2], p1 = sl[3];
+            const bool bad = bk == 1ull || bk == KINF;   // |pivot| zero or non-finite
+            if (bad && fail_code == 0) {
+                fail_code = bk == 1ull ? BTD_ERR_SINGULAR_ : BTD_ERR_NONFINITE_;
+                fail_col = j0 + jj;
+            }
+            const double rp = bad ? 0.0 : rcp;
+            const bool me = row == (int)prw;
+            mypos = me ? j0 + jj : mypos;
+            act = act && !me;
+            const double l = act ? vj * rp : 0.0;
+            v[jj] = act ? l : vj;
+            if (jj + 1 < NB) v[jj + 1] = fma(-l, p1, v[jj + 1]);
+            const double* pr = crow + (size_t)(par * NW + bw) * NB;
+#pragma unroll
+            for (int c = jj + 2; c < NB; ++c) v[c] = fma(-l, pr[c], v[c]);
+            PHASE_MARK(t_s3);
+            PHASE_ADD(7, t_s2, t_s3);
+        }
+    }
 }
 
 template <int NT, int NB>
@@ -446,9 +546,8 @@ __global__ __launch_bounds__(NT) void k_getrf(const KArgs ka) {
     double* Lb = (double*)(smc + lay.lb);
     double* Ub = (double*)(smc + lay.ub);
     double* Tb = (double*)(smc + lay.tb);
-    double* cval = (double*)(smc + lay.cval);
+    double* cslot = (double*)(smc + lay.cval);   // [2][NW][4]: |value|, reciprocal, row
     double* crow = (double*)(smc + lay.crow);
-    int* cidx = (int*)(smc + lay.cidx);
     int* piv = (int*)(smc + lay.piv);
     int* list = (int*)(smc + lay.list);
     int* wcnt = (int*)(smc + lay.wcnt);
@@ -458,69 +557,33 @@ __global__ __launch_bounds__(NT) void k_getrf(const KArgs ka) {
     int mypos = -1;
     int fail_code = 0, fail_col = -1;   // identical in every thread
     const int npan = (M + NB - 1) / NB;
+    double vn[NB];   // the next panel's values of this thread's row
+#pragma unroll
+    for (int c = 0; c < NB; ++c) vn[c] = (act && c < M) ? a[(size_t)row * M + c] : 0.0;
     for (int p = 0; p < npan; ++p) {
         const int j0 = p * NB, nb = min(NB, M - j0);
         PHASE_MARK(t_p0);
         double v[NB];
         const bool act0 = act;
 #pragma unroll
-        for (int c = 0; c < NB; ++c) v[c] = (act && c < nb) ? a[(size_t)row * M + j0 + c] : 0.0;
+        for (int c = 0; c < NB; ++c) v[c] = vn[c];
 
         // ---------------- panel
-#pragma unroll
-        for (int jj = 0; jj < NB; ++jj) {
-            if (jj < nb) {
-                const int par = jj & 1;
-                const double x = act ? (isfinite(v[jj]) ? fabs(v[jj]) : __builtin_inf()) : -1.0;
-                const double wm = wave_max(x);
-                const unsigned long long hit = __ballot(x == wm);
-                const int wl = __ffsll((unsigned long long)hit) - 1;
-                if (lane == wl) {
-                    cval[par * NW + w] = wm;
-                    cidx[par * NW + w] = row;
-                    double* cr = crow + (size_t)(par * NW + w) * NB;
-#pragma unroll
-                    for (int c = jj; c < NB; ++c) cr[c] = v[c];
-                }
-                __syncthreads();
-                double best = cval[par * NW];
-                int bw = 0;
-#pragma unroll
-                for (int q = 1; q < NW; ++q) {
-                    const double cv = cval[par * NW + q];
-                    if (cv > best) { best = cv; bw = q; }
-                }
-                const int prow = cidx[par * NW + bw];
-                const double* pr = crow + (size_t)(par * NW + bw) * NB;
-                const double pv = pr[jj];
-                const bool bad = !isfinite(pv) || pv == 0.0;
-                if (bad && fail_code == 0) {
-                    fail_code = isfinite(pv) ? BTD_ERR_SINGULAR_ : BTD_ERR_NONFINITE_;
-                    fail_col = j0 + jj;
-                }
-                const double rp = bad ? 0.0 : 1.0 / pv;
-                if (row == prow) { act = false; mypos = j0 + jj; }
-                if (tid == 0) piv[jj] = prow;
-                if (act) {
-                    const double l = v[jj] * rp;
-                    v[jj] = l;
-#pragma unroll
-                    for (int c = jj + 1; c < NB; ++c) v[c] = fma(-l, pr[c], v[c]);
-                }
-            }
-        }
+        if (nb == NB) lu_panel_steps<NT, NB, true>(v, act, mypos, fail_code, fail_col, j0, nb, row, lane, w, cslot, crow);
+        else lu_panel_steps<NT, NB, false>(v, act, mypos, fail_code, fail_col, j0, nb, row, lane, w, cslot, crow);
         PHASE_MARK(t_p1);
         PHASE_ADD(0, t_p0, t_p1);
-        // the panel, factored, to the multiplier rows; the multipliers of the
-        // rows not chosen yet also to the working copy
+        // the panel, factored, to the multiplier rows (every row active at the
+        // panel's start) and, for the rows not chosen yet, to the working copy;
+        // the pivot order of the panel; the rows not chosen yet
         if (act0) {
 #pragma unroll
             for (int c = 0; c < NB; ++c) {
-                if (act && c < nb) a[(size_t)row * M + j0 + c] = v[c];
                 Lb[row * LP + c] = v[c];
+                if (act && c < nb) a[(size_t)row * M + j0 + c] = v[c];   // read back when the row is chosen
             }
         }
-        // the rows not chosen yet, listed in row order
+        if (mypos >= j0 && mypos < j0 + nb) piv[mypos - j0] = row;
         {
             const unsigned long long am = __ballot(act);
             if (lane == 0) wcnt[w] = __popcll(am);
@@ -531,7 +594,40 @@ __global__ __launch_bounds__(NT) void k_getrf(const KArgs ka) {
             if (act) list[base + __popcll(am & ((1ull << lane) - 1ull))] = row;
         }
         const int w2 = M - j0 - nb;   // columns right of the panel (0 only after the last panel)
-        if (w2 > 0) {
+        // ---------------- the pivot rows, read once from the working copy: the
+        // multipliers left of the panel go to the factors, A12 to Ub
+        {
+            constexpr int RW = (NB + NW - 1) / NW, CL = NT / 64;
+            double val[RW][CL];
+#pragma unroll
+            for (int q = 0; q < RW; ++q) {
+                const int rr = w + q * NW;
+                const int pr = rr < nb ? piv[rr] : 0;
+#pragma unroll
+                for (int u = 0; u < CL; ++u) {
+                    const int c = lane + 64 * u;
+                    val[q][u] = (rr < nb && c < M && (c < j0 || c >= j0 + nb)) ? a[(size_t)pr * M + c] : 0.0;
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < RW; ++q) {
+                const int rr = w + q * NW;
+                if (rr < nb) {
+                    const int pr = piv[rr];
+#pragma unroll
+                    for (int u = 0; u < CL; ++u) {
+                        const int c = lane + 64 * u;
+                        if (c < j0) out[(size_t)(j0 + rr) * M + c] = val[q][u];
+                        else if (c < j0 + nb) out[(size_t)(j0 + rr) * M + c] = Lb[pr * LP + c - j0];
+                        else if (c < M) Ub[rr * UP + c - j0 - nb] = val[q][u];
+                    }
+                }
+            }
+        }
+        PHASE_MARK(t_p2);
+        PHASE_ADD(1, t_p1, t_p2);
+        if (w2 <= 0) break;
+        __syncthreads();
         // ---------------- inv(L11): two 16 x 16 diagonal blocks by forward
         // substitution (lanes 0..15 the first, 16..31 the second), then the
         // off-diagonal block -inv(L_22) L_21 inv(L_11) on MFMA.
@@ -572,146 +668,134 @@ __global__ __launch_bounds__(NT) void k_getrf(const KArgs ka) {
             for (int vv = 0; vv < 4; ++vv) Tb[(16 + g + 4 * vv) * TP + (lane & 15)] = acc2[vv];
         }
         __syncthreads();
-        // ---------------- U12 = inv(L11) A12, 16-column strips over the waves,
-        // every strip's A12 operands loaded before the first product
-        {
-            constexpr int SPW = (NT - NB + 16 * NW - 1) / (16 * NW);   // strips per wave at most
-            double bop[SPW][KS];
+        // ---------------- U12 = inv(L11) A12 in place in Ub, 16-column strips over
+        // the waves; the rows of U12 are final and go to the factors too
+        for (int cs = w * 16; cs < w2; cs += NW * 16) {
+            const int col = cs + (lane & 15);
+            double bop[KS];
 #pragma unroll
-            for (int sidx = 0; sidx < SPW; ++sidx) {
-                const int col = (w + sidx * NW) * 16 + (lane & 15);
+            for (int kk = 0; kk < KS; ++kk) bop[kk] = col < w2 ? Ub[(4 * kk + g) * UP + col] : 0.0;
 #pragma unroll
-                for (int kk = 0; kk < KS; ++kk)
-                    bop[sidx][kk] = col < w2 ? a[(size_t)piv[4 * kk + g] * M + j0 + nb + col] : 0.0;
-            }
+            for (int x = 0; x < NB / 16; ++x) {
+                v4d acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int sidx = 0; sidx < SPW; ++sidx) {
-                const int cs = (w + sidx * NW) * 16;
-                if (cs < w2) {
-                    const int col = cs + (lane & 15);
+                for (int kk = 0; kk < KS; ++kk) acc = mfma4(Tb[(16 * x + (lane & 15)) * TP + 4 * kk + g], bop[kk], acc);
 #pragma unroll
-                    for (int x = 0; x < NB / 16; ++x) {
-                        v4d acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                        for (int kk = 0; kk < KS; ++kk)
-                            acc = mfma4(Tb[(16 * x + (lane & 15)) * TP + 4 * kk + g], bop[sidx][kk], acc);
-#pragma unroll
-                        for (int vv = 0; vv < 4; ++vv) Ub[(16 * x + g + 4 * vv) * UP + col] = acc[vv];
-                    }
+                for (int vv = 0; vv < 4; ++vv) {
+                    const int rr = 16 * x + g + 4 * vv;
+                    Ub[rr * UP + col] = acc[vv];
+                    if (col < w2) out[(size_t)(j0 + rr) * M + j0 + nb + col] = acc[vv];
                 }
             }
         }
         __syncthreads();
-        }
-        PHASE_MARK(t_p2);
-        PHASE_ADD(1, t_p1, t_p2);
-        // ---------------- the panel's pivot rows, final, in pivot order: one
-        // wave per row, all loads before the stores
-        {
-            constexpr int RW = (NB + NW - 1) / NW, CL = NT / 64;
-            double val[RW][CL];
-#pragma unroll
-            for (int q = 0; q < RW; ++q) {
-                const int rr = w + q * NW;
-                const int pr = rr < nb ? piv[rr] : 0;
-#pragma unroll
-                for (int u = 0; u < CL; ++u) {
-                    const int c = lane + 64 * u;
-                    double x = 0.0;
-                    if (rr < nb && c < M) {
-                        if (c < j0) x = a[(size_t)pr * M + c];
-                        else if (c < j0 + nb) x = Lb[pr * LP + c - j0];
-                        else x = Ub[rr * UP + c - j0 - nb];
-                    }
-                    val[q][u] = x;
-                }
-            }
-#pragma unroll
-            for (int q = 0; q < RW; ++q) {
-                const int rr = w + q * NW;
-#pragma unroll
-                for (int u = 0; u < CL; ++u) {
-                    const int c = lane + 64 * u;
-                    if (rr < nb && c < M) out[(size_t)(j0 + rr) * M + c] = val[q][u];
-                }
-            }
-        }
         PHASE_MARK(t_p3);
         PHASE_ADD(2, t_p2, t_p3);
-        if (w2 <= 0) break;
-        PHASE_MARK(t_p4);
-        // ---------------- A22 -= L21 U12, 32 x 32 tiles, the next tile of the
-        // wave loaded before the current one is multiplied
-        {
-            const int h2 = w2;   // rows not chosen yet
-            const int tc_n = (w2 + 31) / 32, ntiles = ((h2 + 31) / 32) * tc_n;
-            double* a2 = a + j0 + nb;
-            auto load_tile = [&](int tile, v4d (&c)[2][2], int (&crw)[2][4]) {
-                const int tr = (tile / tc_n) * 32, tc = (tile % tc_n) * 32;
+        // ---------------- A22 -= L21 U12 over the rows not chosen yet (list) in
+        // 32 x 32 tiles: first the next panel's columns, then every thread
+        // starts loading its row of the next panel while the other tiles are
+        // updated with their loads three tiles ahead.
+        const int h2 = w2;
+        const int tr_n = (h2 + 31) / 32, tc_n = (w2 + 31) / 32;
+        double* a2 = a + j0 + nb;
+        auto load_tile = [&](int tr, int tc, v4d (&c)[2][2], int (&crw)[2][4]) {
 #pragma unroll
-                for (int x = 0; x < 2; ++x)
+            for (int x = 0; x < 2; ++x)
 #pragma unroll
-                    for (int vv = 0; vv < 4; ++vv) {
-                        const int idx = tr + 16 * x + g + 4 * vv;
-                        crw[x][vv] = idx < h2 ? list[idx] : -1;
-                    }
-#pragma unroll
-                for (int x = 0; x < 2; ++x)
-#pragma unroll
-                    for (int y = 0; y < 2; ++y) {
-                        const int col = tc + 16 * y + (lane & 15);
-#pragma unroll
-                        for (int vv = 0; vv < 4; ++vv)
-                            c[x][y][vv] = (crw[x][vv] >= 0 && col < w2) ? a2[(size_t)crw[x][vv] * M + col] : 0.0;
-                    }
-            };
-            v4d cur[2][2], nxt[2][2];
-            int crw[2][4], nrw[2][4];
-            int tile = w;
-            if (tile < ntiles) load_tile(tile, cur, crw);
-            while (tile < ntiles) {
-                const int tnext = tile + NW;
-                if (tnext < ntiles) load_tile(tnext, nxt, nrw);
-                const int tr = (tile / tc_n) * 32, tc = (tile % tc_n) * 32;
-                int arw[2];
-#pragma unroll
-                for (int x = 0; x < 2; ++x) {
-                    const int idx = tr + 16 * x + (lane & 15);
-                    arw[x] = idx < h2 ? list[idx] : -1;
+                for (int vv = 0; vv < 4; ++vv) {
+                    const int idx = tr + 16 * x + g + 4 * vv;
+                    crw[x][vv] = idx < h2 ? list[idx] : -1;
                 }
 #pragma unroll
-                for (int kk = 0; kk < KS; ++kk) {
-                    double av[2], bv[2];
+            for (int x = 0; x < 2; ++x)
 #pragma unroll
-                    for (int x = 0; x < 2; ++x) av[x] = arw[x] >= 0 ? -Lb[arw[x] * LP + 4 * kk + g] : 0.0;
+                for (int y = 0; y < 2; ++y) {
+                    const int col = tc + 16 * y + (lane & 15);
 #pragma unroll
-                    for (int y = 0; y < 2; ++y) {
-                        const int col = tc + 16 * y + (lane & 15);
-                        bv[y] = col < w2 ? Ub[(4 * kk + g) * UP + col] : 0.0;
-                    }
-#pragma unroll
-                    for (int x = 0; x < 2; ++x)
-#pragma unroll
-                        for (int y = 0; y < 2; ++y) cur[x][y] = mfma4(av[x], bv[y], cur[x][y]);
+                    for (int vv = 0; vv < 4; ++vv)
+                        c[x][y][vv] = (crw[x][vv] >= 0 && col < w2) ? a2[(size_t)crw[x][vv] * M + col] : 0.0;
                 }
+        };
+        auto mul_store = [&](int tr, int tc, v4d (&c)[2][2], const int (&crw)[2][4]) {
+            int arw[2];
 #pragma unroll
-                for (int x = 0; x < 2; ++x)
-#pragma unroll
-                    for (int y = 0; y < 2; ++y) {
-                        const int col = tc + 16 * y + (lane & 15);
-#pragma unroll
-                        for (int vv = 0; vv < 4; ++vv)
-                            if (crw[x][vv] >= 0 && col < w2) a2[(size_t)crw[x][vv] * M + col] = cur[x][y][vv];
-                    }
-#pragma unroll
-                for (int x = 0; x < 2; ++x) {
-#pragma unroll
-                    for (int y = 0; y < 2; ++y) cur[x][y] = nxt[x][y];
-#pragma unroll
-                    for (int vv = 0; vv < 4; ++vv) crw[x][vv] = nrw[x][vv];
-                }
-                tile = tnext;
+            for (int x = 0; x < 2; ++x) {
+                const int idx = tr + 16 * x + (lane & 15);
+                arw[x] = idx < h2 ? list[idx] : -1;
             }
+#pragma unroll
+            for (int kk = 0; kk < KS; ++kk) {
+                double av[2], bv[2];
+#pragma unroll
+                for (int x = 0; x < 2; ++x) av[x] = arw[x] >= 0 ? -Lb[arw[x] * LP + 4 * kk + g] : 0.0;
+#pragma unroll
+                for (int y = 0; y < 2; ++y) {
+                    const int col = tc + 16 * y + (lane & 15);
+                    bv[y] = col < w2 ? Ub[(4 * kk + g) * UP + col] : 0.0;
+                }
+#pragma unroll
+                for (int x = 0; x < 2; ++x)
+#pragma unroll
+                    for (int y = 0; y < 2; ++y) c[x][y] = mfma4(av[x], bv[y], c[x][y]);
+            }
+#pragma unroll
+            for (int x = 0; x < 2; ++x)
+#pragma unroll
+                for (int y = 0; y < 2; ++y) {
+                    const int col = tc + 16 * y + (lane & 15);
+#pragma unroll
+                    for (int vv = 0; vv < 4; ++vv)
+                        if (crw[x][vv] >= 0 && col < w2) a2[(size_t)crw[x][vv] * M + col] = c[x][y][vv];
+                }
+        };
+        {
+            v4d c0[2][2];
+            int q0[2][4];
+            for (int s = w; s < tr_n; s += NW) {
+                load_tile(s * 32, 0, c0, q0);
+                mul_store(s * 32, 0, c0, q0);
+            }
+        }
+        __syncthreads();
+        PHASE_MARK(t_p4);
+        PHASE_ADD(3, t_p3, t_p4);
+        {
+            const int j1 = j0 + nb, nb1 = min(NB, M - j1);
+#pragma unroll
+            for (int c = 0; c < NB; ++c) vn[c] = (act && c < nb1) ? a[(size_t)row * M + j1 + c] : 0.0;
+        }
+        {
+            const int tcr = tc_n - 1, nrest = tr_n * tcr;
+            v4d b0[2][2], b1[2][2], b2[2][2];
+            int q0[2][4], q1[2][4], q2[2][4];
+#define LU_T(s) ((s) / tcr) * 32, (1 + (s) % tcr) * 32
+            int s = w;
+            if constexpr (NW == 4) {
+                // three tiles in flight: the current one and two ahead
+                if (s < nrest) load_tile(LU_T(s), b0, q0);
+                if (s + NW < nrest) load_tile(LU_T(s + NW), b1, q1);
+                for (; s < nrest; s += 3 * NW) {
+                    if (s + 2 * NW < nrest) load_tile(LU_T(s + 2 * NW), b2, q2);
+                    mul_store(LU_T(s), b0, q0);
+                    if (s + NW >= nrest) break;
+                    if (s + 3 * NW < nrest) load_tile(LU_T(s + 3 * NW), b0, q0);
+                    mul_store(LU_T(s + NW), b1, q1);
+                    if (s + 2 * NW >= nrest) break;
+                    if (s + 4 * NW < nrest) load_tile(LU_T(s + 4 * NW), b1, q1);
+                    mul_store(LU_T(s + 2 * NW), b2, q2);
+                }
+            } else {
+                // eight waves: half the registers per wave, one tile ahead
+                if (s < nrest) load_tile(LU_T(s), b0, q0);
+                for (; s < nrest; s += 2 * NW) {
+                    if (s + NW < nrest) load_tile(LU_T(s + NW), b1, q1);
+                    mul_store(LU_T(s), b0, q0);
+                    if (s + NW >= nrest) break;
+                    if (s + 2 * NW < nrest) load_tile(LU_T(s + 2 * NW), b0, q0);
+                    mul_store(LU_T(s + NW), b1, q1);
+                }
+            }
+#undef LU_T
         }
         __syncthreads();
         PHASE_MARK(t_p5);
