@@ -1168,14 +1168,14 @@ __device__ __forceinline__ void trsmw_load(const double* __restrict__ src, int l
     for (int tr = 0; tr < 2; ++tr) {
         const int row = bp * DB + 8 * (i16 & 3) + 4 * tr + (i16 >> 2);
         if (row < M && c0 + 7 < M && (ld & 3) == 0) {
-            const double4* p4 = (const double4*)(src + (size_t)row * ld + c0);
+            const double4* p4 = (const double4*)(src + (uint32_t)(row * ld + c0));
             const double4 v0 = p4[0], v1 = p4[1];
             o[tr][0] = sgn * v0.x; o[tr][1] = sgn * v0.y; o[tr][2] = sgn * v0.z; o[tr][3] = sgn * v0.w;
             o[tr][4] = sgn * v1.x; o[tr][5] = sgn * v1.y; o[tr][6] = sgn * v1.z; o[tr][7] = sgn * v1.w;
         } else {
 #pragma unroll
             for (int kk = 0; kk < 8; ++kk)
-                o[tr][kk] = (row < M && c0 + kk < M) ? sgn * src[(size_t)row * ld + c0 + kk] : 0.0;
+                o[tr][kk] = (row < M && c0 + kk < M) ? sgn * src[(uint32_t)(row * ld + c0 + kk)] : 0.0;
         }
     }
 }
@@ -1238,12 +1238,15 @@ __device__ __forceinline__ void trsmw_diag(v4d (&x)[NBLK][2][NT16], const double
 // RHS = W_i = [C_i | -B_i Y_{i-1}] of the chunk's row at step t; grid =
 // nslab slabs x chunks in one dimension, one wave each, XCD-aware order so
 // that the slabs of one chunk share an L2.
-template <int NBLK, int NT16>
-__global__ __launch_bounds__(64) void k_getrs_w(const KArgs ka, int nslab) {
+template <int NBLK, int NT16, int WPB>
+__global__ __launch_bounds__(64 * WPB) void k_getrs_w(const KArgs ka, int nslab) {
     const Level& L = ka.L;
     const int M = L.M;
-    const int lid = xcd_logical_id(blockIdx.x, gridDim.x);
-    const int k = ka.c0 + lid / nslab, slab = lid % nslab;
+    // WPB consecutive slabs per workgroup: the waves of one CU mostly read the
+    // same factor blocks at about the same time (shared L1)
+    const int wid = xcd_logical_id(blockIdx.x, gridDim.x) * WPB + (int)(threadIdx.x >> 6);
+    if (wid >= nslab * ka.nc) return;
+    const int k = ka.c0 + wid / nslab, slab = wid % nslab;
     const int r = chunk_first(L, k), e = chunk_last(L, k), t = ka.step;
     if (t > e - r) return;
     const int i = r + t;
@@ -1252,7 +1255,7 @@ __global__ __launch_bounds__(64) void k_getrs_w(const KArgs ka, int nslab) {
     const int e_hi = (i != L.N - 1) ? M : 0;          // E_i columns [0, e_hi)
     const int y_hi = (k > 0) ? 2 * M : M;             // Y_i columns [M, y_hi)
     if (!(c0 < e_hi || (c0 < y_hi && c0 + SW > M))) return;
-    const int lane = threadIdx.x, g = lane >> 4, j = lane & 15;
+    const int lane = threadIdx.x & 63, g = lane >> 4, j = lane & 15;
     const int nblk = (M + DB - 1) / DB;
     const double* lu = L.LU + (size_t)i * M * M;
     const double* di = L.DI + (size_t)i * nblk * DI_STRIDE;
@@ -1280,7 +1283,7 @@ __global__ __launch_bounds__(64) void k_getrs_w(const KArgs ka, int nslab) {
                 const bool cv = col < e_hi || (col >= M && col < y_hi);
 #pragma unroll
                 for (int v = 0; v < 4; ++v)
-                    x[b][tr][nt][v] = (cv && prow[b][tr][v] >= 0) ? X[(size_t)prow[b][tr][v] * ld + col] : 0.0;
+                    x[b][tr][nt][v] = (cv && prow[b][tr][v] >= 0) ? X[(uint32_t)(prow[b][tr][v] * ld + col)] : 0.0;
             }
     double o0[2][8], o1[2][8];
     if constexpr (NBLK > 1) {
@@ -1306,7 +1309,206 @@ __global__ __launch_bounds__(64) void k_getrs_w(const KArgs ka, int nslab) {
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int row = b * DB + 8 * g + 4 * tr + v;
-                    if (cv && row < M) X[(size_t)row * ld + col] = x[b][tr][nt][v];
+                    if (cv && row < M) X[(uint32_t)(row * ld + col)] = x[b][tr][nt][v];
+                }
+            }
+}
+
+// ------------------------------------------------------------------ triangular solves, operands shared in LDS
+//
+// As k_getrs_w (same register layout of the right-hand side, same scaled
+// blocks), but a workgroup of WPB waves covers WPB consecutive slabs of one
+// chunk and the 32 x 32 factor blocks go through LDS once per workgroup
+// instead of once per wave: the blocks of the whole sequence (forward block
+// pairs, inverses of the diagonal blocks of L, backward pairs, inverses of
+// the diagonal blocks of U) stream through a ring of four LDS slots, each
+// thread loading one 32-byte piece two blocks ahead, with one barrier per
+// block.  A staged block is stored in operand order: lane l's 16 left
+// operands (two row tiles x eight k) are contiguous, lanes 80 bytes apart,
+// so the reads are free of bank conflicts.
+constexpr int TS_LANE = 10;                  // doubles per lane and row tile in a staged block
+constexpr int TS_BLOCK = 2 * 64 * TS_LANE;   // doubles per staged block
+constexpr int TS_RING = 4;
+
+template <int NBLK>
+__host__ __device__ constexpr int trsm_nseq() { return 2 * (trsm_npairs<NBLK>() + NBLK); }
+
+// Element e of the block sequence: kind 0 forward pair, 1 diagonal of L,
+// 2 backward pair, 3 diagonal of U; source block (b) and target block (bp).
+template <int NBLK>
+__host__ __device__ constexpr int tseq_kind(int e) {
+    constexpr int NP = trsm_npairs<NBLK>();
+    return e < NP ? 0 : e < NP + NBLK ? 1 : e < 2 * NP + NBLK ? 2 : 3;
+}
+template <int NBLK>
+__host__ __device__ constexpr int tseq_b(int e) {
+    constexpr int NP = trsm_npairs<NBLK>();
+    const int k = tseq_kind<NBLK>(e);
+    return k == 0 ? trsm_pair<NBLK>(e, true, true)
+         : k == 1 ? e - NP
+         : k == 2 ? trsm_pair<NBLK>(e - NP - NBLK, false, true)
+                  : e - 2 * NP - NBLK;
+}
+template <int NBLK>
+__host__ __device__ constexpr int tseq_bp(int e) {
+    constexpr int NP = trsm_npairs<NBLK>();
+    const int k = tseq_kind<NBLK>(e);
+    return k == 0 ? trsm_pair<NBLK>(e, true, false)
+         : k == 2 ? trsm_pair<NBLK>(e - NP - NBLK, false, false)
+                  : tseq_b<NBLK>(e);
+}
+
+// This thread's 32-byte piece of sequence element e: row tid / 8 of the
+// block, columns 4 (tid % 8) .. +3 (negated for pairs).
+template <int NBLK>
+__device__ __forceinline__ double4 tseq_load(int e, const double* __restrict__ lu, const double* __restrict__ di,
+                                             int M, int nblk, int tid) {
+    const int kind = tseq_kind<NBLK>(e), b = tseq_b<NBLK>(e), bp = tseq_bp<NBLK>(e);
+    const int r = tid >> 3, c4 = (tid & 7) * 4;
+    double4 v = {0.0, 0.0, 0.0, 0.0};
+    if (kind == 0 || kind == 2) {
+        const int row = bp * DB + r, col = b * DB + c4;
+        if (row < M) {
+            if (col + 3 < M && (M & 3) == 0) {
+                v = *(const double4*)(lu + (uint32_t)(row * M + col));
+            } else {
+                v.x = col < M ? lu[(uint32_t)(row * M + col)] : 0.0;
+                v.y = col + 1 < M ? lu[(uint32_t)(row * M + col + 1)] : 0.0;
+                v.z = col + 2 < M ? lu[(uint32_t)(row * M + col + 2)] : 0.0;
+                v.w = col + 3 < M ? lu[(uint32_t)(row * M + col + 3)] : 0.0;
+            }
+            v.x = -v.x; v.y = -v.y; v.z = -v.z; v.w = -v.w;
+        }
+    } else if (b < nblk) {
+        v = *(const double4*)(di + (size_t)b * DI_STRIDE + (kind == 3 ? DB * DB : 0) + r * DB + c4);
+    }
+    return v;
+}
+
+// Store a piece in operand order: block row r is row tile tr = (r >> 2) & 1,
+// tile row i16 = (r >> 3) | ((r & 3) << 2); column c = 8 g + kk.
+__device__ __forceinline__ void tseq_stage(double* slot, int tid, double4 v) {
+    const int r = tid >> 3, c4 = (tid & 7) * 4;
+    const int tr = (r >> 2) & 1, i16 = (r >> 3) | ((r & 3) << 2);
+    const int g = c4 >> 3, kk = c4 & 7;
+    double* d = slot + (tr * 64 + g * 16 + i16) * TS_LANE + kk;
+    *(double2*)d = make_double2(v.x, v.y);
+    *(double2*)(d + 2) = make_double2(v.z, v.w);
+}
+
+template <int NBLK, int NT16, int E>
+__device__ __forceinline__ void tseq_apply(v4d (&x)[NBLK][2][NT16], const double* slot, int lane) {
+    constexpr int kind = tseq_kind<NBLK>(E), B = tseq_b<NBLK>(E), BP = tseq_bp<NBLK>(E);
+    double o[2][8];
+#pragma unroll
+    for (int tr = 0; tr < 2; ++tr) {
+        const double* src = slot + (tr * 64 + lane) * TS_LANE;
+        const double2 a0 = *(const double2*)src, a1 = *(const double2*)(src + 2);
+        const double2 a2 = *(const double2*)(src + 4), a3 = *(const double2*)(src + 6);
+        o[tr][0] = a0.x; o[tr][1] = a0.y; o[tr][2] = a1.x; o[tr][3] = a1.y;
+        o[tr][4] = a2.x; o[tr][5] = a2.y; o[tr][6] = a3.x; o[tr][7] = a3.y;
+    }
+    if constexpr (kind == 0 || kind == 2) {
+        trsmw_update<NBLK, NT16, B, BP>(x, o);
+    } else {
+        v4d nw[2][NT16];
+#pragma unroll
+        for (int tr = 0; tr < 2; ++tr)
+#pragma unroll
+            for (int nt = 0; nt < NT16; ++nt) nw[tr][nt] = (v4d){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kk = 0; kk < 8; ++kk)
+#pragma unroll
+            for (int tr = 0; tr < 2; ++tr)
+#pragma unroll
+                for (int nt = 0; nt < NT16; ++nt) nw[tr][nt] = mfma4(o[tr][kk], x[B][kk >> 2][nt][kk & 3], nw[tr][nt]);
+#pragma unroll
+        for (int tr = 0; tr < 2; ++tr)
+#pragma unroll
+            for (int nt = 0; nt < NT16; ++nt) x[B][tr][nt] = nw[tr][nt];
+    }
+}
+
+// Sequence element E: stage E+1 (loaded two elements ago), start loading
+// E+3, apply E, barrier.  p0/p1 hold the pieces of E+1 and E+2 on entry.
+template <int NBLK, int NT16, int E>
+__device__ __forceinline__ void tseq_run(v4d (&x)[NBLK][2][NT16], double* ring, const double* __restrict__ lu,
+                                         const double* __restrict__ di, int M, int nblk, int tid, int lane,
+                                         double4& p0, double4& p1) {
+    constexpr int NS = trsm_nseq<NBLK>();
+    if constexpr (E < NS) {
+        if constexpr (E + 1 < NS) tseq_stage(ring + ((E + 1) % TS_RING) * TS_BLOCK, tid, p0);
+        double4 p2 = {0.0, 0.0, 0.0, 0.0};
+        if constexpr (E + 3 < NS) p2 = tseq_load<NBLK>(E + 3, lu, di, M, nblk, tid);
+        tseq_apply<NBLK, NT16, E>(x, ring + (E % TS_RING) * TS_BLOCK, lane);
+        __syncthreads();
+        tseq_run<NBLK, NT16, E + 1>(x, ring, lu, di, M, nblk, tid, lane, p1, p2);
+    }
+}
+
+template <int NBLK, int NT16, int WPB>
+__global__ __launch_bounds__(64 * WPB) void k_getrs_s(const KArgs ka, int nslab, int wpc) {
+    __shared__ double ring[TS_RING * TS_BLOCK];
+    const Level& L = ka.L;
+    const int M = L.M;
+    const int lid = xcd_logical_id(blockIdx.x, gridDim.x);
+    const int k = ka.c0 + lid / wpc, wgc = lid % wpc;
+    const int r = chunk_first(L, k), e = chunk_last(L, k), t = ka.step;
+    if (t > e - r) return;
+    const int i = r + t;
+    constexpr int SW = 16 * NT16;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4, j = lane & 15;
+    const int e_hi = (i != L.N - 1) ? M : 0;          // E_i columns [0, e_hi)
+    const int y_hi = (k > 0) ? 2 * M : M;             // Y_i columns [M, y_hi)
+    const int g0 = wgc * WPB * SW, g1 = min(g0 + WPB * SW, nslab * SW);
+    if (!(g0 < e_hi || (g0 < y_hi && g1 > M))) return;   // nothing to solve in this workgroup
+    const int slab = wgc * WPB + w;
+    const int c0 = slab * SW;
+    const int nblk = (M + DB - 1) / DB;
+    const double* lu = L.LU + (size_t)i * M * M;
+    const double* di = L.DI + (size_t)i * nblk * DI_STRIDE;
+    const int* perm = L.perm + (size_t)i * M;
+    double* X = L.W + (size_t)i * M * 2 * M;
+    const int ld = 2 * M;
+    // first blocks of the sequence in flight before the right-hand side is read
+    double4 p0 = tseq_load<NBLK>(0, lu, di, M, nblk, tid);
+    double4 p1 = tseq_load<NBLK>(1, lu, di, M, nblk, tid);
+    double4 p2 = tseq_load<NBLK>(2, lu, di, M, nblk, tid);
+    v4d x[NBLK][2][NT16];
+#pragma unroll
+    for (int b = 0; b < NBLK; ++b)
+#pragma unroll
+        for (int tr = 0; tr < 2; ++tr) {
+            int prw[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = b * DB + 8 * g + 4 * tr + v;
+                prw[v] = row < M ? perm[row] : -1;
+            }
+#pragma unroll
+            for (int nt = 0; nt < NT16; ++nt) {
+                const int col = c0 + 16 * nt + j;
+                const bool cv = col < e_hi || (col >= M && col < y_hi);
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    x[b][tr][nt][v] = (cv && prw[v] >= 0) ? X[(uint32_t)(prw[v] * ld + col)] : 0.0;
+            }
+        }
+    tseq_stage(ring, tid, p0);
+    __syncthreads();
+    tseq_run<NBLK, NT16, 0>(x, ring, lu, di, M, nblk, tid, lane, p1, p2);
+#pragma unroll
+    for (int b = 0; b < NBLK; ++b)
+#pragma unroll
+        for (int tr = 0; tr < 2; ++tr)
+#pragma unroll
+            for (int nt = 0; nt < NT16; ++nt) {
+                const int col = c0 + 16 * nt + j;
+                const bool cv = col < e_hi || (col >= M && col < y_hi);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = b * DB + 8 * g + 4 * tr + v;
+                    if (cv && row < M) X[(uint32_t)(row * ld + col)] = x[b][tr][nt][v];
                 }
             }
 }
@@ -1620,34 +1822,29 @@ static int slab_width(int M) { return M <= 256 ? 32 : 16; }
 
 template <int NBLK, int NT16>
 static void launch_getrs_w(const KArgs& ka, hipStream_t s) {
+    constexpr int WPB = 4;
     const int nslab = cdiv(2 * ka.L.M, 16 * NT16);
-    hipLaunchKernelGGL((k_getrs_w<NBLK, NT16>), dim3(nslab * ka.nc), dim3(64), 0, s, ka, nslab);
+    hipLaunchKernelGGL((k_getrs_w<NBLK, NT16, WPB>), dim3(cdiv(nslab * ka.nc, WPB)), dim3(64 * WPB), 0, s, ka, nslab);
 }
 
-// M <= 256: one wave per slab, the widest slab (most reuse of each factor
-// operand) that still gives every SIMD of the GPU a wave; above: the
-// workgroup slab kernel.
+template <int NBLK, int NT16>
+static void launch_getrs_s(const KArgs& ka, hipStream_t s) {
+    constexpr int WPB = 4;
+    const int nslab = cdiv(2 * ka.L.M, 16 * NT16), wpc = cdiv(nslab, WPB);
+    hipLaunchKernelGGL((k_getrs_s<NBLK, NT16, WPB>), dim3(wpc * ka.nc), dim3(64 * WPB), 0, s, ka, nslab, wpc);
+}
+
+// M <= 256: slabs of 32 columns (64 for M <= 64) held in one wave's
+// accumulators, four slabs of one chunk per workgroup sharing the factor
+// blocks through LDS; above: the workgroup slab kernel.
 hipError_t launch_getrs(const KArgs& ka, hipStream_t s) {
     const int M = ka.L.M;
     if (M <= 256) {
         const int nblk = cdiv(M, DB);
-        const int nbp = nblk <= 1 ? 1 : nblk <= 2 ? 2 : nblk <= 4 ? 4 : 8;
-        const int simds = 1024;
-        int nt = 1;
-        for (int c = 4; c >= 2; c /= 2)
-            if (nbp * c <= 16 && ka.nc * cdiv(2 * M, 16 * c) >= simds) { nt = c; break; }
-        switch (nbp * 10 + nt) {
-            case 14: launch_getrs_w<1, 4>(ka, s); break;
-            case 11: case 12: launch_getrs_w<1, 4>(ka, s); break;
-            case 21: launch_getrs_w<2, 1>(ka, s); break;
-            case 22: launch_getrs_w<2, 2>(ka, s); break;
-            case 24: launch_getrs_w<2, 4>(ka, s); break;
-            case 41: launch_getrs_w<4, 1>(ka, s); break;
-            case 42: launch_getrs_w<4, 2>(ka, s); break;
-            case 44: launch_getrs_w<4, 4>(ka, s); break;
-            case 81: launch_getrs_w<8, 1>(ka, s); break;
-            default: launch_getrs_w<8, 2>(ka, s); break;
-        }
+        if (nblk <= 1) launch_getrs_s<1, 4>(ka, s);
+        else if (nblk <= 2) launch_getrs_s<2, 4>(ka, s);
+        else if (nblk <= 4) launch_getrs_s<4, 2>(ka, s);
+        else launch_getrs_s<8, 2>(ka, s);
         return hipGetLastError();
     }
     const int sw = slab_width(M);
