@@ -7,7 +7,7 @@ and the on-device FP64 residual check.  Prints ONE JSON line.
 
 Default workload: dense diagonally dominant blocks, N=4096 block rows of
 M=256 (diagonal shift 1.5), R=1 right-hand side, FP64, P=256 subsystems,
-the coupling system solved by the same method two levels deep.
+the coupling systems solved by the same method three levels deep.
 """
 import argparse
 import json
@@ -22,7 +22,7 @@ if ROOT not in sys.path:
 
 METRIC = "block-tridiag solves/s + MFMA TFLOP/s vs peak (N=4096,M=256); p50/p99 latency"
 DEFAULT_P = 256
-DEFAULT_DEPTH = 2
+DEFAULT_DEPTH = 3
 PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 (matrix and vector), vendor datasheet
 PEAK_HBM_GBS = 8000.0
 

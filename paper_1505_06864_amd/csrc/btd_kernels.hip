@@ -1358,42 +1358,52 @@ __host__ __device__ constexpr int tseq_bp(int e) {
                   : tseq_b<NBLK>(e);
 }
 
-// This thread's 32-byte piece of sequence element e: row tid / 8 of the
-// block, columns 4 (tid % 8) .. +3 (negated for pairs).
-template <int NBLK>
+// This thread's piece of sequence element e (PC = 4 or 2 consecutive
+// doubles of one block row; negated for pairs).
+template <int NBLK, int PC>
 __device__ __forceinline__ double4 tseq_load(int e, const double* __restrict__ lu, const double* __restrict__ di,
                                              int M, int nblk, int tid) {
     const int kind = tseq_kind<NBLK>(e), b = tseq_b<NBLK>(e), bp = tseq_bp<NBLK>(e);
-    const int r = tid >> 3, c4 = (tid & 7) * 4;
+    constexpr int PR = DB / PC;   // pieces per block row
+    const int r = tid / PR, c4 = (tid % PR) * PC;
     double4 v = {0.0, 0.0, 0.0, 0.0};
     if (kind == 0 || kind == 2) {
         const int row = bp * DB + r, col = b * DB + c4;
         if (row < M) {
-            if (col + 3 < M && (M & 3) == 0) {
+            if (PC == 4 && col + 3 < M && (M & 3) == 0) {
                 v = *(const double4*)(lu + (uint32_t)(row * M + col));
+            } else if (PC == 2 && col + 1 < M && (M & 1) == 0) {
+                const double2 h = *(const double2*)(lu + (uint32_t)(row * M + col));
+                v.x = h.x; v.y = h.y;
             } else {
                 v.x = col < M ? lu[(uint32_t)(row * M + col)] : 0.0;
                 v.y = col + 1 < M ? lu[(uint32_t)(row * M + col + 1)] : 0.0;
-                v.z = col + 2 < M ? lu[(uint32_t)(row * M + col + 2)] : 0.0;
-                v.w = col + 3 < M ? lu[(uint32_t)(row * M + col + 3)] : 0.0;
+                if (PC == 4) {
+                    v.z = col + 2 < M ? lu[(uint32_t)(row * M + col + 2)] : 0.0;
+                    v.w = col + 3 < M ? lu[(uint32_t)(row * M + col + 3)] : 0.0;
+                }
             }
             v.x = -v.x; v.y = -v.y; v.z = -v.z; v.w = -v.w;
         }
     } else if (b < nblk) {
-        v = *(const double4*)(di + (size_t)b * DI_STRIDE + (kind == 3 ? DB * DB : 0) + r * DB + c4);
+        const double* src = di + (size_t)b * DI_STRIDE + (kind == 3 ? DB * DB : 0) + r * DB + c4;
+        if (PC == 4) v = *(const double4*)src;
+        else { const double2 h = *(const double2*)src; v.x = h.x; v.y = h.y; }
     }
     return v;
 }
 
 // Store a piece in operand order: block row r is row tile tr = (r >> 2) & 1,
 // tile row i16 = (r >> 3) | ((r & 3) << 2); column c = 8 g + kk.
+template <int PC>
 __device__ __forceinline__ void tseq_stage(double* slot, int tid, double4 v) {
-    const int r = tid >> 3, c4 = (tid & 7) * 4;
+    constexpr int PR = DB / PC;
+    const int r = tid / PR, c4 = (tid % PR) * PC;
     const int tr = (r >> 2) & 1, i16 = (r >> 3) | ((r & 3) << 2);
     const int g = c4 >> 3, kk = c4 & 7;
     double* d = slot + (tr * 64 + g * 16 + i16) * TS_LANE + kk;
     *(double2*)d = make_double2(v.x, v.y);
-    *(double2*)(d + 2) = make_double2(v.z, v.w);
+    if (PC == 4) *(double2*)(d + 2) = make_double2(v.z, v.w);
 }
 
 template <int NBLK, int NT16, int E>
@@ -1431,18 +1441,18 @@ __device__ __forceinline__ void tseq_apply(v4d (&x)[NBLK][2][NT16], const double
 
 // Sequence element E: stage E+1 (loaded two elements ago), start loading
 // E+3, apply E, barrier.  p0/p1 hold the pieces of E+1 and E+2 on entry.
-template <int NBLK, int NT16, int E>
+template <int NBLK, int NT16, int PC, int E>
 __device__ __forceinline__ void tseq_run(v4d (&x)[NBLK][2][NT16], double* ring, const double* __restrict__ lu,
                                          const double* __restrict__ di, int M, int nblk, int tid, int lane,
                                          double4& p0, double4& p1) {
     constexpr int NS = trsm_nseq<NBLK>();
     if constexpr (E < NS) {
-        if constexpr (E + 1 < NS) tseq_stage(ring + ((E + 1) % TS_RING) * TS_BLOCK, tid, p0);
+        if constexpr (E + 1 < NS) tseq_stage<PC>(ring + ((E + 1) % TS_RING) * TS_BLOCK, tid, p0);
         double4 p2 = {0.0, 0.0, 0.0, 0.0};
-        if constexpr (E + 3 < NS) p2 = tseq_load<NBLK>(E + 3, lu, di, M, nblk, tid);
+        if constexpr (E + 3 < NS) p2 = tseq_load<NBLK, PC>(E + 3, lu, di, M, nblk, tid);
         tseq_apply<NBLK, NT16, E>(x, ring + (E % TS_RING) * TS_BLOCK, lane);
         __syncthreads();
-        tseq_run<NBLK, NT16, E + 1>(x, ring, lu, di, M, nblk, tid, lane, p1, p2);
+        tseq_run<NBLK, NT16, PC, E + 1>(x, ring, lu, di, M, nblk, tid, lane, p1, p2);
     }
 }
 
@@ -1471,9 +1481,10 @@ __global__ __launch_bounds__(64 * WPB) void k_getrs_s(const KArgs ka, int nslab,
     double* X = L.W + (size_t)i * M * 2 * M;
     const int ld = 2 * M;
     // first blocks of the sequence in flight before the right-hand side is read
-    double4 p0 = tseq_load<NBLK>(0, lu, di, M, nblk, tid);
-    double4 p1 = tseq_load<NBLK>(1, lu, di, M, nblk, tid);
-    double4 p2 = tseq_load<NBLK>(2, lu, di, M, nblk, tid);
+    constexpr int PC = 1024 / (64 * WPB);   // doubles of a staged block per thread
+    double4 p0 = tseq_load<NBLK, PC>(0, lu, di, M, nblk, tid);
+    double4 p1 = tseq_load<NBLK, PC>(1, lu, di, M, nblk, tid);
+    double4 p2 = tseq_load<NBLK, PC>(2, lu, di, M, nblk, tid);
     v4d x[NBLK][2][NT16];
 #pragma unroll
     for (int b = 0; b < NBLK; ++b)
@@ -1494,9 +1505,9 @@ __global__ __launch_bounds__(64 * WPB) void k_getrs_s(const KArgs ka, int nslab,
                     x[b][tr][nt][v] = (cv && prw[v] >= 0) ? X[(uint32_t)(prw[v] * ld + col)] : 0.0;
             }
         }
-    tseq_stage(ring, tid, p0);
+    tseq_stage<PC>(ring, tid, p0);
     __syncthreads();
-    tseq_run<NBLK, NT16, 0>(x, ring, lu, di, M, nblk, tid, lane, p1, p2);
+    tseq_run<NBLK, NT16, PC, 0>(x, ring, lu, di, M, nblk, tid, lane, p1, p2);
 #pragma unroll
     for (int b = 0; b < NBLK; ++b)
 #pragma unroll

@@ -157,15 +157,15 @@ StreamPool* stream_pool() {
 }
 
 // Groups for a level of P chunks: at least 8 chunks per group, at most
-// BTD_STREAM_GROUPS (environment, 1..4; default 1: one stream, measured
-// faster on MI355X than concurrent groups once every chunk's step fills
-// the GPU by itself).
+// BTD_STREAM_GROUPS (environment, 1..4; default 2: on MI355X two groups
+// let one group's LU overlap the other's products and triangular solves,
+// more groups starve each other of CUs).
 int chunk_groups(int P) {
     static int cap = -1;
     if (cap < 0) {
         const char* env = std::getenv("BTD_STREAM_GROUPS");
         const int v = env ? std::atoi(env) : 0;
-        cap = (v >= 1 && v <= kMaxGroups) ? v : 1;
+        cap = (v >= 1 && v <= kMaxGroups) ? v : 2;
     }
     int g = P / 8;
     return g < 1 ? 1 : (g > cap ? cap : g);
