@@ -7,7 +7,8 @@ and the on-device FP64 residual check.  Prints ONE JSON line.
 
 Default workload: dense diagonally dominant blocks, N=4096 block rows of
 M=256 (diagonal shift 1.5), R=1 right-hand side, FP64, P=256 subsystems,
-the coupling systems solved by the same method three levels deep.
+the coupling systems solved recursively by the same method with subsystems
+of one row (coupling_rows = 1, at most 10 levels).
 """
 import argparse
 import json
@@ -22,7 +23,8 @@ if ROOT not in sys.path:
 
 METRIC = "block-tridiag solves/s + MFMA TFLOP/s vs peak (N=4096,M=256); p50/p99 latency"
 DEFAULT_P = 256
-DEFAULT_DEPTH = 3
+DEFAULT_DEPTH = 10
+DEFAULT_COUPLING_ROWS = 1   # 0: Eq. SuppMatrM; k >= 1: coupling subsystems of about k rows
 PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 (matrix and vector), vendor datasheet
 PEAK_HBM_GBS = 8000.0
 
@@ -43,6 +45,7 @@ def parse():
     ap.add_argument("--workload", default="large", choices=sorted(WORKLOADS))
     ap.add_argument("--P", type=int, default=None)
     ap.add_argument("--depth", type=int, default=None)
+    ap.add_argument("--coupling-rows", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-rows", type=int, default=None)
     ap.add_argument("--roofline-class", default="auto")
@@ -81,7 +84,7 @@ def make_inputs(torch, name, dev):
 class Runner:
     """Direct C-ABI calls with preallocated workspaces (no allocation per step)."""
 
-    def __init__(self, torch, A, B, C, F, P, depth):
+    def __init__(self, torch, A, B, C, F, P, depth, coupling_rows=0):
         import ctypes
         from paper_1505_06864_amd import btd
         self.ct, self.btd, self.torch = ctypes, btd, torch
@@ -89,8 +92,8 @@ class Runner:
         self.N, self.M, _ = A.shape
         self.R = F.shape[2]
         self.A, self.B, self.C, self.F = A, B, C, F
-        self.desc, self._keep = btd.make_desc(self.N, self.M, P, depth, self.R)
-        fb, sb = btd.workspace_bytes(self.N, self.M, P, depth, self.R)
+        self.desc, self._keep = btd.make_desc(self.N, self.M, P, depth, self.R, None, coupling_rows)
+        fb, sb = btd.workspace_bytes(self.N, self.M, P, depth, self.R, None, coupling_rows)
         self.fws, self.fptr = btd._aligned_buffer(fb, A.device)
         self.sws, self.sptr = btd._aligned_buffer(sb, A.device)
         self.fb, self.sb = fb, sb
@@ -194,15 +197,16 @@ def main():
     N, M, R, gen = WORKLOADS[args.workload]
     P = args.P if args.P is not None else (DEFAULT_P if N >= 1024 else 4)
     depth = args.depth if args.depth is not None else DEFAULT_DEPTH
+    crow = args.coupling_rows if args.coupling_rows is not None else DEFAULT_COUPLING_ROWS
     (A, B, C, F), host = make_inputs(torch, args.workload, dev)
-    run = Runner(torch, A, B, C, F, P, depth)
+    run = Runner(torch, A, B, C, F, P, depth, crow)
 
     for _ in range(args.warmup):
         run.step()
     torch.cuda.synchronize()
     run.release()
 
-    per = flops.per_class(N, M, R, P, depth, R)
+    per = flops.per_class(N, M, R, P, depth, R, None, crow)
     # pick the kernel class with the largest device time (one untimed step per class)
     class_ms = {}
     for c in btd.KERNEL_CLASSES:
@@ -232,7 +236,7 @@ def main():
     resid = float(run.res.max().item())
     run.release()
 
-    fac, sol = flops.totals(N, M, R, P, depth, R)
+    fac, sol = flops.totals(N, M, R, P, depth, R, None, crow)
     ms_step = wall * 1e3 / args.steps
     # per launch = the class's algorithmic FLOPs over the launches actually made (chunk groups on
     # several streams split one step into several launches)
@@ -254,7 +258,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {gen} blocks, N={N}, M={M}, R={R}, FP64",
-                   "N": N, "M": M, "R": R, "P": P, "depth": depth},
+                   "N": N, "M": M, "R": R, "P": P, "depth": depth, "coupling_rows": crow},
         "tflops": tflops,
         "frac_fp64_peak": tflops / PEAK_FP64_TFLOPS,
         "gflop_per_solve": (fac + sol) / 1e9,

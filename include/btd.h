@@ -85,10 +85,19 @@ typedef struct btd_plan_s *btd_plan_t;
  *             array of P-1 strictly increasing 0-based separator rows with
  *             1 <= q, q <= N-2 and at least one row between neighbours.
  *             Copied during btd_factor; not retained.
+ *   coupling_rows  how the coupling systems of the recursion levels are
+ *             split: 0 = m from Eq. SuppMatrM as described under depth (the
+ *             choice that minimises the operation count of Sec. 5); k >= 1 =
+ *             subsystems of about k rows, m = floor((Nc + 1) / (k + 1)) for a
+ *             coupling system of Nc rows (at least 2; the Thomas algorithm
+ *             when Nc < 3).  Small k trades extra operations for fewer
+ *             sequential steps, which is what bounds a recursion level on a
+ *             GPU.
  */
 typedef struct {
     int32_t N, M, P, depth, prec, max_nrhs;
     const int32_t *seps;
+    int32_t coupling_rows;
 } btd_desc_t;
 
 /*
@@ -180,6 +189,10 @@ int btd_plan_level_parts(btd_plan_t plan, int32_t level);
  * Both return -1 for invalid sizes. */
 int btd_default_separators(int32_t N, int32_t P, int32_t *seps_out);
 int btd_default_coupling_parts(int32_t P, int32_t M, int32_t R);
+/* Subsystem count of the coupling system of a level with P subsystems for a
+ * given coupling_rows (see btd_desc_t; 0 gives btd_default_coupling_parts).
+ * Returns -1 for invalid sizes. */
+int btd_coupling_parts(int32_t P, int32_t M, int32_t R, int32_t coupling_rows);
 
 /*
  * Kernel timing for measurements: while a class is enabled, every launch of

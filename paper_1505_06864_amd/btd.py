@@ -23,7 +23,8 @@ BTD_MAX_M = 512
 # Every symbol include/btd.h declares.
 EXPORTS = ("btd_workspace_bytes", "btd_factor", "btd_solve", "btd_solve_batch", "btd_residual_work_bytes",
            "btd_residual", "btd_get_info", "btd_plan_separators", "btd_plan_level_parts",
-           "btd_default_separators", "btd_default_coupling_parts", "btd_profile_enable", "btd_profile_read",
+           "btd_default_separators", "btd_default_coupling_parts", "btd_coupling_parts", "btd_profile_enable",
+           "btd_profile_read",
            "btd_plan_destroy", "btd_status_string")
 
 # Kernel classes of btd_profile_enable (BTD_KC_*).
@@ -34,7 +35,7 @@ KERNEL_CLASSES = ("fwd_gemm", "getrf", "getrs_factor", "bwd_gemm", "couple", "rh
 class Desc(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int32), ("M", ctypes.c_int32), ("P", ctypes.c_int32),
                 ("depth", ctypes.c_int32), ("prec", ctypes.c_int32), ("max_nrhs", ctypes.c_int32),
-                ("seps", ctypes.POINTER(ctypes.c_int32))]
+                ("seps", ctypes.POINTER(ctypes.c_int32)), ("coupling_rows", ctypes.c_int32)]
 
 
 _lib = None
@@ -61,6 +62,7 @@ def lib():
         L.btd_plan_level_parts.argtypes = [vp, i32]
         L.btd_default_separators.argtypes = [i32, i32, ctypes.POINTER(i32)]
         L.btd_default_coupling_parts.argtypes = [i32, i32, i32]
+        L.btd_coupling_parts.argtypes = [i32, i32, i32, i32]
         L.btd_profile_enable.argtypes = [i32]
         L.btd_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
         L.btd_plan_destroy.argtypes = [vp]
@@ -107,8 +109,8 @@ def _aligned_buffer(nbytes, device):
     return buf, ptr
 
 
-def make_desc(N, M, P=1, depth=0, max_nrhs=1, seps=None):
-    d = Desc(N, M, P, depth, BTD_PREC_F64, max_nrhs, None)
+def make_desc(N, M, P=1, depth=0, max_nrhs=1, seps=None, coupling_rows=0):
+    d = Desc(N, M, P, depth, BTD_PREC_F64, max_nrhs, None, coupling_rows)
     keep = None
     if seps is not None:
         keep = (ctypes.c_int32 * max(len(seps), 1))(*[int(q) for q in seps])
@@ -116,9 +118,9 @@ def make_desc(N, M, P=1, depth=0, max_nrhs=1, seps=None):
     return d, keep
 
 
-def workspace_bytes(N, M, P=1, depth=0, max_nrhs=1, seps=None):
+def workspace_bytes(N, M, P=1, depth=0, max_nrhs=1, seps=None, coupling_rows=0):
     """(factor bytes, solve bytes) for a description; raises on an invalid one."""
-    d, _keep = make_desc(N, M, P, depth, max_nrhs, seps)
+    d, _keep = make_desc(N, M, P, depth, max_nrhs, seps, coupling_rows)
     f, s = ctypes.c_size_t(), ctypes.c_size_t()
     rc = lib().btd_workspace_bytes(ctypes.byref(d), ctypes.byref(f), ctypes.byref(s))
     if rc != BTD_OK:
@@ -136,26 +138,34 @@ def default_separators(N, P):
 
 
 def default_coupling_parts(P, M, R):
-    """Subsystem count of the recursive coupling solve (host only)."""
+    """Subsystem count of the recursive coupling solve, Eq. SuppMatrM (host only)."""
     rc = lib().btd_default_coupling_parts(P, M, R)
     if rc < 0:
         raise BtdError(rc, "btd_default_coupling_parts")
     return rc
 
 
+def coupling_parts(P, M, R, coupling_rows=0):
+    """Subsystem count of the coupling solve for a coupling_rows setting (host only)."""
+    rc = lib().btd_coupling_parts(P, M, R, coupling_rows)
+    if rc < 0:
+        raise BtdError(rc, "btd_coupling_parts")
+    return rc
+
+
 class Plan:
     """A factored system (btd_factor).  Keeps A, B, C and the factor workspace alive."""
 
-    def __init__(self, A, B, C, P=1, depth=0, max_nrhs=1, seps=None, stream=None):
+    def __init__(self, A, B, C, P=1, depth=0, max_nrhs=1, seps=None, stream=None, coupling_rows=0):
         N, M = A.shape[0], A.shape[1]
         for t, n in ((A, "A"), (B, "B"), (C, "C")):
             _check(t, n, (N, M, M))
         self.N, self.M, self.P, self.depth, self.max_nrhs = N, M, P, depth, max_nrhs
         self.device = A.device
         self.A, self.B, self.C = A, B, C
-        fbytes, self.solve_bytes = workspace_bytes(N, M, P, depth, max_nrhs, seps)
+        fbytes, self.solve_bytes = workspace_bytes(N, M, P, depth, max_nrhs, seps, coupling_rows)
         self._ws, ptr = _aligned_buffer(fbytes, A.device)
-        d, _keep = make_desc(N, M, P, depth, max_nrhs, seps)
+        d, _keep = make_desc(N, M, P, depth, max_nrhs, seps, coupling_rows)
         h = ctypes.c_void_p()
         rc = lib().btd_factor(ctypes.byref(d), A.data_ptr(), B.data_ptr(), C.data_ptr(), ptr, fbytes,
                               _stream_handle(stream, A.device), ctypes.byref(h))
@@ -219,8 +229,8 @@ class Plan:
             pass
 
 
-def factor(A, B, C, P=1, depth=0, max_nrhs=1, seps=None, stream=None):
-    return Plan(A, B, C, P=P, depth=depth, max_nrhs=max_nrhs, seps=seps, stream=stream)
+def factor(A, B, C, P=1, depth=0, max_nrhs=1, seps=None, stream=None, coupling_rows=0):
+    return Plan(A, B, C, P=P, depth=depth, max_nrhs=max_nrhs, seps=seps, stream=stream, coupling_rows=coupling_rows)
 
 
 def solve_batch(plans, Fs, Xs=None, stream=None):

@@ -42,13 +42,20 @@ void equal_split(int N, int P, std::vector<int>& sep) {
     }
 }
 
-// Subsystem count of the coupling system for a recursive level
-// (Eq. SuppMatrM, capped at floor(P/3), at least 2; 1 = Thomas algorithm).
-int coupling_parts(int P, int M, int R) {
+// Subsystem count of the coupling system (P-1 rows) of a level with P
+// subsystems.  k = 0: Eq. SuppMatrM, capped at floor(P/3), at least 2;
+// k >= 1: subsystems of about k rows.  1 = Thomas algorithm (fewer than 3
+// rows).
+int coupling_parts(int P, int M, int R, int k = 0) {
     if (P - 1 < 3) return 1;
-    const double ms = std::sqrt((double)P / 3.0 * (5.0 + 2.0 / (1.0 + (double)R / (double)M)));
-    int m = (int)std::floor(ms + 0.5);
-    if (m > P / 3) m = P / 3;
+    int m;
+    if (k <= 0) {
+        const double ms = std::sqrt((double)P / 3.0 * (5.0 + 2.0 / (1.0 + (double)R / (double)M)));
+        m = (int)std::floor(ms + 0.5);
+        if (m > P / 3) m = P / 3;
+    } else {
+        m = P / (k + 1);   // (Nc + 1) / (k + 1) with Nc = P - 1
+    }
     if (m < 2) m = 2;
     return m;
 }
@@ -56,6 +63,7 @@ int coupling_parts(int P, int M, int R) {
 bool valid_desc(const btd_desc_t* d) {
     if (!d) return false;
     if (d->N < 1 || d->M < 1 || d->M > BTD_MAX_M || d->P < 1 || d->depth < 0 || d->max_nrhs < 1) return false;
+    if (d->coupling_rows < 0) return false;
     if (d->prec != BTD_PREC_F64) return false;
     if (d->P > 1 && 2 * (int64_t)d->P - 1 > d->N) return false;
     if (d->N > (1 << 24) - 1) return false;
@@ -111,7 +119,7 @@ size_t build_levels(const btd_desc_t* d, std::vector<LevelPlan>& lv) {
         lv.push_back(L);
         if (P == 1) break;
         const int Nc = P - 1;
-        const int Pc = (depth > 0) ? coupling_parts(P, M, d->max_nrhs) : 1;
+        const int Pc = (depth > 0) ? coupling_parts(P, M, d->max_nrhs, d->coupling_rows) : 1;
         N = Nc;
         P = Pc;
         depth = depth > 0 ? depth - 1 : 0;
@@ -476,6 +484,11 @@ int btd_default_separators(int32_t N, int32_t P, int32_t* seps_out) {
 int btd_default_coupling_parts(int32_t P, int32_t M, int32_t R) {
     if (P < 1 || M < 1 || R < 1) return -1;
     return coupling_parts(P, M, R);
+}
+
+int btd_coupling_parts(int32_t P, int32_t M, int32_t R, int32_t coupling_rows) {
+    if (P < 1 || M < 1 || R < 1 || coupling_rows < 0) return -1;
+    return coupling_parts(P, M, R, coupling_rows);
 }
 
 int btd_profile_enable(int32_t kernel_class) {

@@ -15,7 +15,7 @@ from . import btd
 CLASSES = btd.KERNEL_CLASSES
 
 
-def levels(N, M, P, depth, max_nrhs, seps=None):
+def levels(N, M, P, depth, max_nrhs, seps=None, coupling_rows=0):
     """[(N_l, P_l, separators_l)] of every recursion level of a plan."""
     out = []
     top = True
@@ -24,7 +24,7 @@ def levels(N, M, P, depth, max_nrhs, seps=None):
         out.append((N, P, s))
         if P == 1:
             return out
-        Pc = btd.default_coupling_parts(P, M, max_nrhs) if depth > 0 else 1
+        Pc = btd.coupling_parts(P, M, max_nrhs, coupling_rows) if depth > 0 else 1
         N, P, depth, top = P - 1, Pc, max(depth - 1, 0), False
 
 
@@ -33,7 +33,7 @@ def chunk_sizes(N, P, seps):
     return [b[k + 1] - b[k] - 1 for k in range(P)]
 
 
-def per_class(N, M, R, P, depth=0, max_nrhs=None, seps=None):
+def per_class(N, M, R, P, depth=0, max_nrhs=None, seps=None, coupling_rows=0):
     """Dict kernel class -> (total algorithmic FLOPs, number of launch steps).
 
     The launch-step count is that of one stream; when the plan splits a
@@ -45,7 +45,7 @@ def per_class(N, M, R, P, depth=0, max_nrhs=None, seps=None):
     M3, M2R = float(M) ** 3, float(M) ** 2 * R
     tot = {c: 0.0 for c in CLASSES}
     launches = {c: 0 for c in CLASSES}
-    for (Nl, Pl, s) in levels(N, M, P, depth, max_nrhs, seps):
+    for (Nl, Pl, s) in levels(N, M, P, depth, max_nrhs, seps, coupling_rows):
         nk = chunk_sizes(Nl, Pl, s)
         nmax = max(nk)
         for k, n in enumerate(nk):
@@ -83,9 +83,9 @@ FACTOR_CLASSES = ("fwd_gemm", "getrf", "getrs_factor", "bwd_gemm", "couple")
 SOLVE_CLASSES = ("rhs_sweep", "couple_rhs", "recover")
 
 
-def totals(N, M, R, P, depth=0, max_nrhs=None, seps=None):
+def totals(N, M, R, P, depth=0, max_nrhs=None, seps=None, coupling_rows=0):
     """(factor FLOPs, solve FLOPs) of the method (residual excluded)."""
-    pc = per_class(N, M, R, P, depth, max_nrhs, seps)
+    pc = per_class(N, M, R, P, depth, max_nrhs, seps, coupling_rows)
     return sum(pc[c][0] for c in FACTOR_CLASSES), sum(pc[c][0] for c in SOLVE_CLASSES)
 
 

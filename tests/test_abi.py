@@ -86,6 +86,26 @@ def test_coupling_parts_match_oracle():
             assert btd.default_coupling_parts(P, M, R) == oracle.default_m(P, M, R), (P, M, R)
 
 
+def test_coupling_rows_rule():
+    """coupling_rows = k splits a coupling system of P-1 rows into
+    floor(P/(k+1)) subsystems (at least 2, Thomas algorithm below 3 rows);
+    0 is Eq. SuppMatrM; negative values are rejected before any device work."""
+    for P in range(1, 300):
+        assert btd.coupling_parts(P, 64, 1, 0) == btd.default_coupling_parts(P, 64, 1)
+        for k in (1, 2, 3, 7):
+            m = btd.coupling_parts(P, 64, 1, k)
+            if P - 1 < 3:
+                assert m == 1
+            else:
+                assert m == max(2, P // (k + 1))
+                # every subsystem of the coupling system keeps at least one row
+                assert 2 * m - 1 <= P - 1
+    with pytest.raises(btd.BtdError):
+        btd.coupling_parts(8, 4, 1, -1)
+    with pytest.raises(btd.BtdError):
+        btd.workspace_bytes(64, 4, 8, 2, 1, None, -1)
+
+
 @pytest.mark.parametrize("N,M,R,P,depth,seps", [(64, 16, 1, 4, 0, None), (64, 16, 3, 16, 1, None),
                                                 (40, 8, 2, 5, 0, [1, 15, 21, 33]), (300, 4, 2, 40, 2, None),
                                                 (57, 2, 1, 1, 0, None)])

@@ -18,10 +18,11 @@ TOL_X = 1e-10
 TOL_RES = 1e-12
 
 
-def run_gpu(torch, A, B, C, F, P, depth=0, seps=None, max_nrhs=None, inplace=False):
+def run_gpu(torch, A, B, C, F, P, depth=0, seps=None, max_nrhs=None, inplace=False, coupling_rows=0):
     Ad, Bd, Cd, Fd = to_dev(torch, A, B, C, F)
     R = F.shape[2]
-    plan = btd.factor(Ad, Bd, Cd, P=P, depth=depth, max_nrhs=max_nrhs or R, seps=seps)
+    plan = btd.factor(Ad, Bd, Cd, P=P, depth=depth, max_nrhs=max_nrhs or R, seps=seps,
+                      coupling_rows=coupling_rows)
     Xd = plan.solve(Fd, Fd if inplace else None)
     st = plan.info()
     assert st == (0, -1, -1), st
@@ -32,9 +33,10 @@ def run_gpu(torch, A, B, C, F, P, depth=0, seps=None, max_nrhs=None, inplace=Fal
     return X, res
 
 
-def check_case(torch, A, B, C, F, P, depth=0, seps=None, inplace=False):
-    print(f"case N={A.shape[0]} M={A.shape[1]} R={F.shape[2]} P={P} depth={depth} seps={seps}", flush=True)
-    X, res_gpu = run_gpu(torch, A, B, C, F, P, depth, seps, inplace=inplace)
+def check_case(torch, A, B, C, F, P, depth=0, seps=None, inplace=False, coupling_rows=0):
+    print(f"case N={A.shape[0]} M={A.shape[1]} R={F.shape[2]} P={P} depth={depth} seps={seps} "
+          f"coupling_rows={coupling_rows}", flush=True)
+    X, res_gpu = run_gpu(torch, A, B, C, F, P, depth, seps, inplace=inplace, coupling_rows=coupling_rows)
     Xo = oracle.dm_solve(A, B, C, F, P, seps=seps, depth=depth)
     assert_parity(X, Xo, TOL_X)
     res = oracle.residual(A, B, C, X, F)
@@ -126,6 +128,15 @@ def test_deterministic():
     assert np.array_equal(X1, X2)
 
 
+@pytest.mark.parametrize("coupling_rows,depth", [(1, 8), (2, 4), (3, 2)])
+def test_coupling_rows_split(coupling_rows, depth):
+    """Coupling systems split into subsystems of about k rows instead of Eq.
+    SuppMatrM: same solution (the oracle uses the paper's m)."""
+    torch = require_gpu()
+    A, B, C, F = inputs.diag_dominant(400, 24, 3, seed=41, shift=2.0)
+    check_case(torch, A, B, C, F, 64, depth, coupling_rows=coupling_rows)
+
+
 def test_pivoting_needed():
     """Diagonal blocks whose leading entries are zero: LU without row
     interchanges would break down."""
@@ -210,9 +221,9 @@ def test_large_workload_full_size():
     torch = require_gpu()
     N, M, R = 4096, 256, 1
     A, B, C, F, xs = inputs.diag_dominant(N, M, R, seed=2, shift=1.5, want_xstar=True)
-    from bench import DEFAULT_P, DEFAULT_DEPTH
-    print(f"large N={N} M={M} P={DEFAULT_P} depth={DEFAULT_DEPTH}", flush=True)
-    X, res_gpu = run_gpu(torch, A, B, C, F, DEFAULT_P, DEFAULT_DEPTH)
+    from bench import DEFAULT_P, DEFAULT_DEPTH, DEFAULT_COUPLING_ROWS
+    print(f"large N={N} M={M} P={DEFAULT_P} depth={DEFAULT_DEPTH} coupling_rows={DEFAULT_COUPLING_ROWS}", flush=True)
+    X, res_gpu = run_gpu(torch, A, B, C, F, DEFAULT_P, DEFAULT_DEPTH, coupling_rows=DEFAULT_COUPLING_ROWS)
     res = oracle.residual(A, B, C, X, F)
     assert res.max() <= TOL_RES, res
     assert res_gpu.max() <= TOL_RES, res_gpu
