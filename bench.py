@@ -157,7 +157,7 @@ def cpu_baseline(host_inputs, P, depth, rows, workload):
                        f"scaled to the full workload by the algorithmic-FLOP ratio {f_full / f_s:.1f}")}
 
 
-def recorded_traffic(kclass, workload, P, depth):
+def recorded_traffic(kclass, workload, P, depth, coupling_rows):
     """HBM bytes per launch of a kernel class from the committed rocprofv3
     counter summary (FETCH_SIZE + WRITE_SIZE, each scaled against a plain copy
     kernel), or None when there is none for this workload and plan or the
@@ -175,7 +175,8 @@ def recorded_traffic(kclass, workload, P, depth):
     src = os.path.join(ROOT, "paper_1505_06864_amd", "csrc", "btd_kernels.hip")
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
     if (kv.get("kernel_source_sha256") != sha or kv.get("kernel_class") != kclass
-            or kv.get("P") != str(P) or kv.get("depth") != str(depth)):
+            or kv.get("P") != str(P) or kv.get("depth") != str(depth)
+            or kv.get("coupling_rows") != str(coupling_rows)):
         return None
     return float(kv["hbm_bytes_per_launch"])
 
@@ -268,7 +269,7 @@ def main():
         "kernel_ms_per_step": {c: round(v, 3) for c, v in class_ms.items()},
         "roofline": {"kernel": dom, "bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
-                     "traffic": recorded_traffic(dom, args.workload, P, depth),
+                     "traffic": recorded_traffic(dom, args.workload, P, depth, crow),
                      "avg_launch_ms": dom_avg_ms, "launches": dom_n,
                      "gflop_per_launch": dom_flops_per_launch / 1e9},
     }
