@@ -100,6 +100,16 @@ __device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
     return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
 }
 
+// Sum over the 64 lanes with DPP row operations and four readlanes (the
+// same association for every call, so results are deterministic).
+__device__ __forceinline__ double wave_sum(double v) {
+    v += dpp_mov<0xB1>(v);    // quad_perm [1,0,3,2]
+    v += dpp_mov<0x4E>(v);    // quad_perm [2,3,0,1]
+    v += dpp_mov<0x141>(v);   // row_half_mirror
+    v += dpp_mov<0x140>(v);   // row_mirror
+    return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
+}
+
 // Workgroup copy of n elements with UNR loads in flight per thread before
 // the matching stores (a plain strided loop waits for every load).
 template <int UNR, class LD, class ST>
@@ -1730,41 +1740,92 @@ __global__ void k_write_ints(int* dst, int count, IntChunk vals) {
 // ------------------------------------------------------------------ residual
 //
 // r = F - (B X_{i-1} + A X_i + C X_{i+1}); per column sum of squares of r
-// and of F.  One workgroup per block row writes its partial sums (no
-// atomics: the reduction order is fixed); a second kernel sums them.
+// and of F.  One workgroup per (block row, column); each wave takes whole
+// rows, its lanes covering the row in 32-byte pieces (one coalesced read of
+// the row of A_i, B_i and C_i per 256 columns), the matching pieces of the
+// three X columns held in registers, four rows in flight, and a DPP sum per
+// row.  The workgroup writes its partial sums (no atomics: the reduction
+// order is fixed); a second kernel sums them.
 __global__ __launch_bounds__(256) void k_residual_rows(int N, int M, int R, const double* __restrict__ A,
                                                       const double* __restrict__ B, const double* __restrict__ C,
                                                       const double* __restrict__ X, const double* __restrict__ F,
                                                       double* __restrict__ part) {
     const int i = blockIdx.x, c = blockIdx.y;
     const size_t MM = (size_t)M * M, MR = (size_t)M * R;
-    __shared__ double sr[256], sf[256];
-    double accr = 0.0, accf = 0.0;
+    __shared__ double sr[4], sf[4];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    for (int row = w; row < M; row += 4) {
-        double s = 0.0;
-        for (int kk = lane; kk < M; kk += 64) {
-            s += A[i * MM + (size_t)row * M + kk] * X[i * MR + (size_t)kk * R + c];
-            if (i > 0) s += B[i * MM + (size_t)row * M + kk] * X[(i - 1) * MR + (size_t)kk * R + c];
-            if (i < N - 1) s += C[i * MM + (size_t)row * M + kk] * X[(i + 1) * MR + (size_t)kk * R + c];
-        }
+    const bool hasb = i > 0, hasc = i < N - 1;
+    double accr = 0.0, accf = 0.0;
+    if ((M & 255) == 0 && M <= 512) {
+        // lane l covers columns 4l..4l+3 of every 256-column piece
+        constexpr int MAXP = BTD_MAX_M / 256;
+        const int np = M / 256;
+        double xa[MAXP][4], xb[MAXP][4], xc[MAXP][4];
 #pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
-        if (lane == 0) {
+        for (int q = 0; q < MAXP; ++q)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int k = q * 256 + 4 * lane + e;
+                const bool ok = q < np;
+                xa[q][e] = ok ? X[i * MR + (size_t)k * R + c] : 0.0;
+                xb[q][e] = (ok && hasb) ? X[(i - 1) * MR + (size_t)k * R + c] : 0.0;
+                xc[q][e] = (ok && hasc) ? X[(i + 1) * MR + (size_t)k * R + c] : 0.0;
+            }
+        for (int r0 = w * 4; r0 < M; r0 += 16) {
+            double s[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const size_t ro = i * MM + (size_t)(r0 + u) * M + 4 * lane;
+                double acc = 0.0;
+#pragma unroll
+                for (int q = 0; q < MAXP; ++q) {
+                    if (q < np) {
+                        const double4 va = *(const double4*)(A + ro + q * 256);
+                        acc = fma(va.x, xa[q][0], acc); acc = fma(va.y, xa[q][1], acc);
+                        acc = fma(va.z, xa[q][2], acc); acc = fma(va.w, xa[q][3], acc);
+                        if (hasb) {
+                            const double4 vb = *(const double4*)(B + ro + q * 256);
+                            acc = fma(vb.x, xb[q][0], acc); acc = fma(vb.y, xb[q][1], acc);
+                            acc = fma(vb.z, xb[q][2], acc); acc = fma(vb.w, xb[q][3], acc);
+                        }
+                        if (hasc) {
+                            const double4 vc = *(const double4*)(C + ro + q * 256);
+                            acc = fma(vc.x, xc[q][0], acc); acc = fma(vc.y, xc[q][1], acc);
+                            acc = fma(vc.z, xc[q][2], acc); acc = fma(vc.w, xc[q][3], acc);
+                        }
+                    }
+                }
+                s[u] = acc;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const double tot = wave_sum(s[u]);
+                const double f = F[i * MR + (size_t)(r0 + u) * R + c];
+                const double rv = f - tot;
+                accr += rv * rv;
+                accf += f * f;
+            }
+        }
+    } else {
+        for (int row = w; row < M; row += 4) {
+            double acc = 0.0;
+            for (int kk = lane; kk < M; kk += 64) {
+                acc = fma(A[i * MM + (size_t)row * M + kk], X[i * MR + (size_t)kk * R + c], acc);
+                if (hasb) acc = fma(B[i * MM + (size_t)row * M + kk], X[(i - 1) * MR + (size_t)kk * R + c], acc);
+                if (hasc) acc = fma(C[i * MM + (size_t)row * M + kk], X[(i + 1) * MR + (size_t)kk * R + c], acc);
+            }
+            const double tot = wave_sum(acc);
             const double f = F[i * MR + (size_t)row * R + c];
-            const double rv = f - s;
+            const double rv = f - tot;
             accr += rv * rv;
             accf += f * f;
         }
     }
-    sr[threadIdx.x] = accr;
-    sf[threadIdx.x] = accf;
+    if (lane == 0) { sr[w] = accr; sf[w] = accf; }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double a = 0.0, b = 0.0;
-        for (int q = 0; q < 4; ++q) { a += sr[q * 64]; b += sf[q * 64]; }
-        part[((size_t)c * N + i) * 2 + 0] = a;
-        part[((size_t)c * N + i) * 2 + 1] = b;
+        part[((size_t)c * N + i) * 2 + 0] = (sr[0] + sr[1]) + (sr[2] + sr[3]);
+        part[((size_t)c * N + i) * 2 + 1] = (sf[0] + sf[1]) + (sf[2] + sf[3]);
     }
 }
 
