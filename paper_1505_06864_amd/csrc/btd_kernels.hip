@@ -1737,6 +1737,77 @@ __global__ void k_write_ints(int* dst, int count, IntChunk vals) {
     if (t < count) dst[t] = vals.v[t];
 }
 
+// ------------------------------------------------------------------ recovery, few right-hand sides
+//
+// X_i -= Z_L[i] h^{k-1} + Z_R[i] h^k (Eq. endSolution) for R <= RC and M a
+// multiple of 128: one workgroup per block row; each wave takes whole rows
+// of Z_i = [Z_L | Z_R] with its lanes covering the row in 32-byte pieces,
+// the matching pieces of [h^{k-1}; h^k] held in registers, four rows in
+// flight and a DPP sum per row (an HBM stream of 16 M^2 bytes per block row
+// for 4 M^2 R FLOPs).  Separator rows take their value from the coupling
+// solution.
+template <int RC>
+__global__ __launch_bounds__(256) void k_recover_v(const KArgs ka) {
+    const Level& L = ka.L;
+    const int i = blockIdx.x, M = L.M, R = ka.R, P = L.P;
+    const size_t MR = (size_t)M * R, MM = (size_t)M * M;
+    int lo = 0, hi = P;   // chunk k with sep[k] <= i < sep[k+1]  (sep[0] = -1, sep[P] = N)
+    while (hi - lo > 1) { const int mid = (lo + hi) >> 1; if (L.sep[mid] <= i) lo = mid; else hi = mid; }
+    const int k = lo;
+    double* Xi = ka.X + i * MR;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (L.sep[k] == i) {   // separator row: X_q = h^k
+        for (int e = threadIdx.x; e < (int)MR; e += 256) Xi[e] = ka.Fc[(size_t)(k - 1) * MR + e];
+        return;
+    }
+    const bool left = k > 0, right = k < P - 1;
+    // lane l covers columns 4l..4l+3 of every 256-column piece of the 2M columns
+    constexpr int MAXP = 2 * BTD_MAX_M / 256;
+    const int np = 2 * M / 256;
+    double hv[MAXP][4][RC];
+#pragma unroll
+    for (int q = 0; q < MAXP; ++q)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int kk = q * 256 + 4 * lane + e;   // 0..2M-1: h^{k-1} rows then h^k rows
+            const bool isl = kk < M;
+            const bool ok = q < np && (isl ? left : right);
+            const double* hsrc = ka.Fc + (size_t)(isl ? k - 1 : k) * MR + (size_t)(isl ? kk : kk - M) * R;
+#pragma unroll
+            for (int c = 0; c < RC; ++c) hv[q][e][c] = (ok && c < R) ? hsrc[c] : 0.0;
+        }
+    const double* Zi = L.Z + i * MM * 2;
+    for (int r0 = w * 4; r0 < M; r0 += 16) {
+        double s[4][RC];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+#pragma unroll
+            for (int c = 0; c < RC; ++c) s[u][c] = 0.0;
+            const double* z = Zi + (size_t)(r0 + u) * 2 * M + 4 * lane;
+#pragma unroll
+            for (int q = 0; q < MAXP; ++q)
+                if (q < np) {
+                    const double4 zz = *(const double4*)(z + q * 256);
+#pragma unroll
+                    for (int c = 0; c < RC; ++c) {
+                        s[u][c] = fma(zz.x, hv[q][0][c], s[u][c]);
+                        s[u][c] = fma(zz.y, hv[q][1][c], s[u][c]);
+                        s[u][c] = fma(zz.z, hv[q][2][c], s[u][c]);
+                        s[u][c] = fma(zz.w, hv[q][3][c], s[u][c]);
+                    }
+                }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int c = 0; c < RC; ++c)
+                if (c < R) {
+                    const double tot = wave_sum(s[u][c]);
+                    if (lane == 0) Xi[(size_t)(r0 + u) * R + c] -= tot;
+                }
+    }
+}
+
 // ------------------------------------------------------------------ residual
 //
 // r = F - (B X_{i-1} + A X_i + C X_{i+1}); per column sum of squares of r
@@ -1864,7 +1935,13 @@ hipError_t launch_fwd_gemm(const KArgs& ka, hipStream_t s) { return launch_gemm<
 hipError_t launch_bwd_gemm(const KArgs& ka, hipStream_t s) { return launch_gemm<GM_BWD, 2>(ka, ka.nc, ka.L.M, ka.L.M, s); }
 hipError_t launch_couple(const KArgs& ka, hipStream_t s) { return launch_gemm<GM_COUPLE, 3>(ka, ka.L.P - 1, ka.L.M, ka.L.M, s); }
 hipError_t launch_couple_rhs(const KArgs& ka, hipStream_t s) { return launch_gemm<GM_COUPLE_RHS, 1>(ka, ka.L.P - 1, ka.L.M, ka.R, s); }
-hipError_t launch_recover(const KArgs& ka, hipStream_t s) { return launch_gemm<GM_RECOVER, 1>(ka, ka.L.N, ka.L.M, ka.R, s); }
+hipError_t launch_recover(const KArgs& ka, hipStream_t s) {
+    if (ka.R == 1 && ka.L.M % 128 == 0) {
+        hipLaunchKernelGGL((k_recover_v<1>), dim3(ka.L.N), dim3(256), 0, s, ka);
+        return hipGetLastError();
+    }
+    return launch_gemm<GM_RECOVER, 1>(ka, ka.L.N, ka.L.M, ka.R, s);
+}
 
 // One thread per row: 256 threads and 32-column panels up to M = 256,
 // 512 threads and 16-column panels above (the LDS holds the multiplier rows
