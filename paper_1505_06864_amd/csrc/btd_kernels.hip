@@ -285,8 +285,11 @@ __device__ bool make_job(const KArgs& ka, int b, int part, Job& j) {
 // quadrant (w >> 1, w & 1) as 2 x 2 tiles of v_mfma_f64_16x16x4f64.
 // MFMA operand layout (lane l): A element (row l&15, k l>>4); B element
 // (k l>>4, col l&15); D holds rows (l>>4)+4*v, col l&15 in register v.
-// LDS: As[16][64+AP] (k-major, transposed), Bs[16][64+BP].
+// LDS: two buffers of As[16][64+AP] (k-major, transposed) and Bs[16][64+BP];
+// the next K step is loaded (32-byte pieces when the rows are 32-byte
+// aligned) while the current one is multiplied, one barrier per K step.
 constexpr int TB = 64, KB = 16, AP = 4, BP = 4;
+constexpr int ASZ = KB * (TB + AP), BSZ = KB * (TB + BP);
 
 __device__ __forceinline__ void load_tiles(const double* __restrict__ A, int lda, const double* __restrict__ Bm,
                                            int ldb, int row0, int col0, int k0, int m, int n, int K, double ra[4],
@@ -294,20 +297,24 @@ __device__ __forceinline__ void load_tiles(const double* __restrict__ A, int lda
     const int tid = threadIdx.x;
     {
         const int rr = tid >> 2, kq = (tid & 3) * 4;
-        const int gr = row0 + rr;
+        const int gr = row0 + rr, gk = k0 + kq;
+        if (gr < m && gk + 3 < K && (lda & 3) == 0) {
+            const double4 x = *(const double4*)(A + (size_t)gr * lda + gk);
+            ra[0] = x.x; ra[1] = x.y; ra[2] = x.z; ra[3] = x.w;
+        } else {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int gk = k0 + kq + q;
-            ra[q] = (gr < m && gk < K) ? A[(size_t)gr * lda + gk] : 0.0;
+            for (int q = 0; q < 4; ++q) ra[q] = (gr < m && gk + q < K) ? A[(size_t)gr * lda + gk + q] : 0.0;
         }
     }
     {
         const int kk = tid >> 4, cq = (tid & 15) * 4;
-        const int gk = k0 + kk;
+        const int gk = k0 + kk, gc = col0 + cq;
+        if (gk < K && gc + 3 < n && (ldb & 3) == 0) {
+            const double4 x = *(const double4*)(Bm + (size_t)gk * ldb + gc);
+            rb[0] = x.x; rb[1] = x.y; rb[2] = x.z; rb[3] = x.w;
+        } else {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int gc = col0 + cq + q;
-            rb[q] = (gk < K && gc < n) ? Bm[(size_t)gk * ldb + gc] : 0.0;
+            for (int q = 0; q < 4; ++q) rb[q] = (gk < K && gc + q < n) ? Bm[(size_t)gk * ldb + gc + q] : 0.0;
         }
     }
 }
@@ -321,8 +328,7 @@ __device__ __forceinline__ void store_tiles(double* As, double* Bs, const double
     }
     {
         const int kk = tid >> 4, cq = (tid & 15) * 4;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) Bs[kk * (TB + BP) + cq + q] = rb[q];
+        *(double4*)(Bs + kk * (TB + BP) + cq) = make_double4(rb[0], rb[1], rb[2], rb[3]);
     }
 }
 
@@ -333,30 +339,37 @@ __device__ void tile_accumulate(const double* __restrict__ A, int lda, const dou
     double ra[4], rb[4];
     if (K <= 0) return;
     load_tiles(A, lda, Bm, ldb, row0, col0, 0, m, n, K, ra, rb);
+    __syncthreads();   // the buffers may still be read by a previous accumulation
+    store_tiles(As, Bs, ra, rb);
+    __syncthreads();
+    int buf = 0;
     for (int k0 = 0; k0 < K; k0 += KB) {
-        __syncthreads();
-        store_tiles(As, Bs, ra, rb);
-        __syncthreads();
-        if (k0 + KB < K) load_tiles(A, lda, Bm, ldb, row0, col0, k0 + KB, m, n, K, ra, rb);
+        const bool more = k0 + KB < K;
+        if (more) load_tiles(A, lda, Bm, ldb, row0, col0, k0 + KB, m, n, K, ra, rb);
+        const double* as = As + buf * ASZ;
+        const double* bs = Bs + buf * BSZ;
 #pragma unroll
         for (int kk = 0; kk < KB / 4; ++kk) {
             const int krow = kk * 4 + (lane >> 4);
-            double a0 = As[krow * (TB + AP) + wr + (lane & 15)];
-            double a1 = As[krow * (TB + AP) + wr + 16 + (lane & 15)];
-            double b0 = Bs[krow * (TB + BP) + wc + (lane & 15)];
-            double b1 = Bs[krow * (TB + BP) + wc + 16 + (lane & 15)];
+            double a0 = as[krow * (TB + AP) + wr + (lane & 15)];
+            double a1 = as[krow * (TB + AP) + wr + 16 + (lane & 15)];
+            double b0 = bs[krow * (TB + BP) + wc + (lane & 15)];
+            double b1 = bs[krow * (TB + BP) + wc + 16 + (lane & 15)];
             acc[0][0] = mfma4(a0, b0, acc[0][0]);
             acc[0][1] = mfma4(a0, b1, acc[0][1]);
             acc[1][0] = mfma4(a1, b0, acc[1][0]);
             acc[1][1] = mfma4(a1, b1, acc[1][1]);
         }
+        if (more) store_tiles(As + (buf ^ 1) * ASZ, Bs + (buf ^ 1) * BSZ, ra, rb);
+        __syncthreads();
+        buf ^= 1;
     }
 }
 
 template <int MODE, int NPARTS>
 __global__ __launch_bounds__(256) void k_gemm(const KArgs ka, int tiles_m, int tiles_n) {
-    __shared__ double As[KB * (TB + AP)];
-    __shared__ double Bs[KB * (TB + BP)];
+    __shared__ double As[2 * ASZ];
+    __shared__ double Bs[2 * BSZ];
     const int per_item = tiles_m * tiles_n * NPARTS;
     const int lid = xcd_logical_id(blockIdx.x, gridDim.x);
     const int b = lid / per_item;
