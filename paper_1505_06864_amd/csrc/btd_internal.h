@@ -11,7 +11,6 @@ namespace btd {
 
 #define BTD_ERR_SINGULAR_ BTD_ERR_SINGULAR
 #define BTD_ERR_NONFINITE_ BTD_ERR_NONFINITE
-#define BTD_ERR_LAUNCH_ BTD_ERR_LAUNCH
 
 // One level of the method: a block-tridiagonal system of N rows split into
 // P chunks.  Level 0 is the caller's system; level l+1 is the coupling system

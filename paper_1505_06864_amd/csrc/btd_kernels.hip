@@ -480,7 +480,7 @@ __device__ __forceinline__ void lu_panel_steps(double (&v)[NB], bool& act, int& 
     constexpr unsigned long long KINF = 0x7FF0000000000001ull;   // key of a non-finite value
 #pragma unroll
     for (int jj = 0; jj < NB; ++jj) {
-        if (FULL || jj < nb) {
+        if (jj < nb) {
             PHASE_MARK(t_s0);
             const int par = jj & 1;
             const double vj = v[jj];
@@ -831,136 +831,142 @@ __global__ __launch_bounds__(NT) void k_getrf(const KArgs ka) {
     if (tid == 0 && fail_code != 0) report_status(ka.status, L.level, i, fail_col, fail_code);
 }
 
-// ------------------------------------------------------------------ LU with a concurrent update (M <= 256)
+// ------------------------------------------------------------------ LU, one panel wave
 //
 // The factorisation of k_getrf (rows fixed in the working copy, factors
-// written in pivot order, 32-column panels) with eight waves in two roles so
-// that the trailing update overlaps the pivot chain: waves 0..3 own the rows
-// (thread t < 256 holds row t of the panel) and run the column steps of
-// panel p, synchronising among themselves through an LDS counter (they never
-// wait for the other waves inside a panel); at the same time waves 4..7
-// apply panel p-1's update to the columns right of panel p.  All eight waves
-// then share the steps between panels (pivot rows, U12, the next panel's
-// columns, which reach the row owners through LDS).
-constexpr int LU8_NB = 32, LU8_NT = 512, LU8_NP = 4;   // panel width, threads, row-owning waves
-constexpr unsigned LU8_SPIN_LIMIT = 1u << 22;          // bounded waits: a broken count fails, never hangs
+// written in pivot order) for M <= 256 with the pivot chain on a single
+// wave, so that a column step needs no workgroup synchronisation: wave 0
+// holds rows 4l .. 4l+3 of a 16-column panel in lane l (64 registers of
+// doubles) and finds each pivot with a lane-local maximum and a DPP maximum;
+// the pivot's lane passes the rest of the pivot row through LDS (a 16-value
+// slot, written by one lane and read back by all).  Waves 1..7 work one
+// panel behind:
+// while wave 0 factors panel p they apply panel p-1 to the columns right of
+// panel p (U12 = inv(L11) A12 and A22 -= L21 U12 in 16-column slabs on MFMA)
+// and copy the finished factor rows; the columns of panel p+1 are kept in
+// LDS.  Between panels only the next panel's columns are brought up to date
+// (U12 of those 16 columns, then 16 columns of the update on all waves).
+// Ties in the pivot search go to the lowest row, as in the other kernels.
+constexpr int LW_NB = 16, LW_NT = 512, LW_HW = LW_NT / 64 - 1;   // panel width, threads, helper waves
+constexpr int LW_P = LW_NB + 1;                                  // LDS row pitch (doubles)
 
-
-struct Lu8Lds {
-    int LP, UP, TP, SP;
-    size_t lb, ub, tb, slot, crow, piv, list, lpos, wcnt, cnt, total;
+struct LwLds {
+    size_t nx, lb, tb, un, list, piv, prow, total;
 };
 
-__host__ __device__ inline Lu8Lds lu8_lds_layout(int M) {
-    Lu8Lds l;
-    constexpr int NB = LU8_NB;
-    l.LP = NB + 2;
-    l.TP = NB + 2;
-    l.SP = NB + 1;
-    const int w2 = M > NB ? M - NB : 1;
-    l.UP = ((w2 + 31) / 32) * 32 + 16;   // also holds the hand-over [w2][SP] (w2 * SP <= NB * UP)
+// nx: the columns of the next two panels, [2][256][LW_P] by row; lb: the
+// panel rows (multipliers, pivot rows) of the last two panels, by row;
+// tb: inv(L11); un: U12 of the next panel; list: rows not yet chosen, in
+// row order, of the last two panels; piv: pivot rows of the last two panels;
+// prow: the pivot row of the current column step.
+__host__ __device__ constexpr LwLds lw_lds_layout() {
+    LwLds l{};
     size_t off = 0;
-    l.lb = off; off += sizeof(double) * 256 * l.LP;
-    l.ub = off; off += sizeof(double) * (size_t)NB * l.UP;
-    l.tb = off; off += sizeof(double) * (size_t)NB * l.TP;
-    l.slot = off; off += sizeof(double) * 2 * LU8_NP * 4;
-    l.crow = off; off += sizeof(double) * 2 * LU8_NP * (size_t)NB;
-    l.piv = off; off += sizeof(int) * NB;
-    l.list = off; off += sizeof(int) * 256;
-    l.lpos = off; off += sizeof(int) * 256;
-    l.wcnt = off; off += sizeof(int) * 8;
-    l.cnt = off; off += sizeof(unsigned) * 4;
+    l.nx = off; off += sizeof(double) * 2 * 256 * LW_P;
+    l.lb = off; off += sizeof(double) * 2 * 256 * LW_P;
+    l.tb = off; off += sizeof(double) * LW_NB * LW_P;
+    l.un = off; off += sizeof(double) * LW_NB * LW_P;
+    l.list = off; off += sizeof(int) * 2 * 256;
+    l.piv = off; off += sizeof(int) * 2 * LW_NB;
+    l.prow = off; off += sizeof(double) * LW_NB;
     l.total = (off + 15) & ~(size_t)15;
     return l;
 }
 
-// Column steps of one panel on the four row-owning waves (see
-// lu_panel_steps); instead of a workgroup barrier each wave adds one to an
-// LDS counter after publishing its candidate and waits until all four have.
-template <bool FULL>
-__device__ __forceinline__ void lu8_panel_steps(double (&v)[LU8_NB], bool& act, int& mypos, int& fail_code,
-                                                int& fail_col, int j0, int nb, int row, int lane, int w,
-                                                double* cslot, double* crow, unsigned* cnt, unsigned& sc) {
-    constexpr int NB = LU8_NB, NW = LU8_NP;
+// The column steps of one panel on one wave; v[r][c] is column j0+c of row
+// 4*lane+r, act[r] whether that row is still a candidate.
+__device__ __forceinline__ void lw_panel_steps(double (&v)[4][LW_NB], bool (&act)[4], int& fail_code, int& fail_col,
+                                               int j0, int nb, int lane, int* piv, double* prow) {
+    constexpr int NB = LW_NB;
     constexpr unsigned long long KINF = 0x7FF0000000000001ull;
 #pragma unroll
     for (int jj = 0; jj < NB; ++jj) {
-        if (FULL || jj < nb) {
-            const int par = sc & 1;
-            const double vj = v[jj];
-            const unsigned long long bits =
-                isfinite(vj) ? (unsigned long long)__double_as_longlong(fabs(vj)) + 1ull : KINF;
-            const unsigned long long key = act ? bits : 0ull;
-            double r = __builtin_amdgcn_rcp(vj);
-            r = fma(r, fma(-vj, r, 1.0), r);
-            r = fma(r, fma(-vj, r, 1.0), r);
-            const unsigned hi = (unsigned)(key >> 32);
+        if (jj < nb) {
+            // the lane's candidate: largest |value| of its rows, lowest row on ties
+            unsigned long long kb = 0ull;
+            int rb = 0;
+            double vb = 1.0;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const double x = v[r][jj];
+                const unsigned long long bits =
+                    isfinite(x) ? (unsigned long long)__double_as_longlong(fabs(x)) + 1ull : KINF;
+                const unsigned long long key = act[r] ? bits : 0ull;
+                const bool tk = key > kb;
+                kb = tk ? key : kb;
+                rb = tk ? r : rb;
+                vb = tk ? x : vb;
+            }
+            double rc = __builtin_amdgcn_rcp(vb);
+            rc = fma(rc, fma(-vb, rc, 1.0), rc);
+            rc = fma(rc, fma(-vb, rc, 1.0), rc);
+            // the wave's maximum key; its lowest lane holds the lowest row
+            const unsigned hi = (unsigned)(kb >> 32);
             const unsigned mhi = wave_max_u32(hi);
             unsigned long long tied = __ballot(hi == mhi);
             if (__popcll(tied) > 1) {
-                const unsigned lo = hi == mhi ? (unsigned)key : 0u;
+                const unsigned lo = hi == mhi ? (unsigned)kb : 0u;
                 const unsigned mlo = wave_max_u32(lo);
                 tied = __ballot(hi == mhi && lo == mlo);
             }
             const int wl = __ffsll((unsigned long long)tied) - 1;
-            if (lane == wl) {
-                double* sl = cslot + (par * NW + w) * 4;
-                sl[0] = __longlong_as_double((long long)key);
-                sl[1] = r;
-                sl[2] = (double)row;
-                if (jj + 1 < NB) sl[3] = v[jj + 1];
-                double* cr = crow + (size_t)(par * NW + w) * NB;
-#pragma unroll
-                for (int c = jj + 2; c < NB; ++c) cr[c] = v[c];
-            }
-            wave_lds_sync();
-            ++sc;
-            if (lane == 0) __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            {
-                const unsigned target = NW * sc;
-                unsigned it = 0;
-                while (true) {
-                    const unsigned cv = __hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                    if ((unsigned)__builtin_amdgcn_readfirstlane((int)cv) >= target) break;
-                    if (++it > LU8_SPIN_LIMIT) { fail_code = BTD_ERR_LAUNCH_; fail_col = j0 + jj; break; }
-                    __builtin_amdgcn_s_sleep(1);
-                }
-            }
-            const unsigned long long* skey = (const unsigned long long*)cslot;
-            unsigned long long kq[NW];
-#pragma unroll
-            for (int q = 0; q < NW; ++q) kq[q] = skey[(par * NW + q) * 4];
-            unsigned long long bk = kq[0];
-            int bw = 0;
-#pragma unroll
-            for (int q = 1; q < NW; ++q) {
-                const bool tk = kq[q] > bk;
-                bk = tk ? kq[q] : bk;
-                bw = tk ? q : bw;
-            }
-            const double* sl = cslot + (par * NW + bw) * 4;
-            const double rcp = sl[1], prw = sl[2], p1 = sl[3];
+            const int rs = __builtin_amdgcn_readlane(rb, wl);
+            const unsigned long long bk =
+                ((unsigned long long)(unsigned)__builtin_amdgcn_readlane((int)(kb >> 32), wl) << 32) |
+                (unsigned)__builtin_amdgcn_readlane((int)kb, wl);
             const bool bad = bk == 1ull || bk == KINF;
             if (bad && fail_code == 0) {
                 fail_code = bk == 1ull ? BTD_ERR_SINGULAR_ : BTD_ERR_NONFINITE_;
                 fail_col = j0 + jj;
             }
-            const double rp = bad ? 0.0 : rcp;
-            const bool me = row == (int)prw;
-            mypos = me ? j0 + jj : mypos;
-            act = act && !me;
-            const double l = act ? vj * rp : 0.0;
-            v[jj] = act ? l : vj;
-            if (jj + 1 < NB) v[jj + 1] = fma(-l, p1, v[jj + 1]);
-            const double* pr = crow + (size_t)(par * NW + bw) * NB;
+            const double rp = bad ? 0.0 : readlane_d(rc, wl);
+            if (lane == 0) piv[jj] = 4 * wl + rs;
+            // the rest of the pivot row, through LDS from its lane
+            if (rs == 0) {
+                if (lane == wl) {
 #pragma unroll
-            for (int c = jj + 2; c < NB; ++c) v[c] = fma(-l, pr[c], v[c]);
+                    for (int c = 0; c < NB; ++c) if (c > jj) prow[c] = v[0][c];
+                }
+                __asm__ volatile("; pivot row in slot 0");
+            } else if (rs == 1) {
+                if (lane == wl) {
+#pragma unroll
+                    for (int c = 0; c < NB; ++c) if (c > jj) prow[c] = v[1][c];
+                }
+                __asm__ volatile("; pivot row in slot 1");
+            } else if (rs == 2) {
+                if (lane == wl) {
+#pragma unroll
+                    for (int c = 0; c < NB; ++c) if (c > jj) prow[c] = v[2][c];
+                }
+                __asm__ volatile("; pivot row in slot 2");
+            } else {
+                if (lane == wl) {
+#pragma unroll
+                    for (int c = 0; c < NB; ++c) if (c > jj) prow[c] = v[3][c];
+                }
+                __asm__ volatile("; pivot row in slot 3");
+            }
+            wave_lds_sync();
+            double pr[NB];
+#pragma unroll
+            for (int c = 0; c < NB; ++c) pr[c] = c > jj ? prow[c] : 0.0;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const bool me = lane == wl && r == rs;
+                act[r] = act[r] && !me;
+                const double l = act[r] ? v[r][jj] * rp : 0.0;
+                v[r][jj] = act[r] ? l : v[r][jj];
+#pragma unroll
+                for (int c = 0; c < NB; ++c)
+                    if (c > jj) v[r][c] = fma(-l, pr[c], v[r][c]);
+            }
         }
     }
 }
 
-__global__ __launch_bounds__(LU8_NT) void k_getrf8(const KArgs ka) {
-    constexpr int NB = LU8_NB, NW = LU8_NT / 64, KS = NB / 4;
+__global__ __launch_bounds__(LW_NT) void k_getrf_pw(const KArgs ka) {
+    constexpr int NB = LW_NB, P = LW_P;
     const Level& L = ka.L;
     const int kch = ka.c0 + blockIdx.x, t = ka.step;
     const int r0 = chunk_first(L, kch), e = chunk_last(L, kch);
@@ -970,313 +976,215 @@ __global__ __launch_bounds__(LU8_NT) void k_getrf8(const KArgs ka) {
     const int tid = threadIdx.x, lane0 = tid & 63, w = tid >> 6;
     double* a = L.Dw + (size_t)kch * M * M;      // working copy, rows in place
     double* out = L.LU + (size_t)i * M * M;      // factors, rows in pivot order
+    int* perm = L.perm + (size_t)i * M;
     extern __shared__ double sm_raw[];
     char* smc = (char*)sm_raw;
-    const Lu8Lds lay = lu8_lds_layout(M);
-    const int LP = lay.LP, UP = lay.UP, TP = lay.TP, SP = lay.SP;
-    double* Lb = (double*)(smc + lay.lb);
-    double* Ub = (double*)(smc + lay.ub);
-    double* Tb = (double*)(smc + lay.tb);
-    double* cslot = (double*)(smc + lay.slot);
-    double* crow = (double*)(smc + lay.crow);
-    int* piv = (int*)(smc + lay.piv);
-    int* list = (int*)(smc + lay.list);
-    int* lpos = (int*)(smc + lay.lpos);
-    int* wcnt = (int*)(smc + lay.wcnt);
-    unsigned* cnt = (unsigned*)(smc + lay.cnt);
-    const bool owner = w < LU8_NP;
-    const int row = tid;   // rows of the owning waves
-    bool act = owner && row < M;
-    int mypos = -1;
-    int fail_code = 0, fail_col = -1;
-    unsigned sc = 0;
-    if (tid == 0) *cnt = 0u;
-    __syncthreads();
+    constexpr LwLds lay = lw_lds_layout();
+    double* NX = (double*)(smc + lay.nx);
+    double* LB = (double*)(smc + lay.lb);
+    double* TB = (double*)(smc + lay.tb);
+    double* UN = (double*)(smc + lay.un);
+    int* LIST = (int*)(smc + lay.list);
+    int* PIV = (int*)(smc + lay.piv);
+    double* PROW = (double*)(smc + lay.prow);
     const int npan = (M + NB - 1) / NB;
-    int pj0 = 0, pnb = 0, ph2 = 0;   // previous panel, for the update of waves 4..7
-    for (int p = 0; p < npan; ++p) {
+
+    // the columns of panels 0 and 1 of every row
+    for (int idx = tid; idx < 2 * 256 * NB; idx += LW_NT) {
+        const int b = idx / (256 * NB), rem = idx % (256 * NB), row = rem / NB, c = rem % NB;
+        const int col = b * NB + c;
+        NX[(b * 256 + row) * P + c] = (row < M && col < M) ? a[(size_t)row * M + col] : 0.0;
+    }
+    __syncthreads();
+
+    bool act[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) act[r] = w == 0 && 4 * lane0 + r < M;
+    int fail_code = 0, fail_col = -1;
+    int p = 0;
+    for (;; ++p) {
         int lv = lane0;
         __asm__ volatile("" : "+v"(lv));   // keep per-lane addresses from being hoisted out of the loop
-        const int lane = lv, g = lv >> 4;
+        const int lane = lv, g = lv >> 4, cc = lv & 15;
         const int j0 = p * NB, nb = min(NB, M - j0);
-        const int w2 = M - j0 - nb;
-        PHASE_MARK(q0t);
-        if (owner) {
-            // ---------------- panel p on the row owners
-            double v[NB];
-            const int at = (p > 0 && act) ? lpos[row] : 0;
+        const int w2 = M - j0 - nb;          // columns right of panel p = rows left after it
+        const int cur = p & 1, nxt = cur ^ 1;
+        if (w == 0) {
+            // ---------------- panel p
+            double v[4][NB];
 #pragma unroll
-            for (int c = 0; c < NB; ++c)
-                v[c] = !(act && c < nb) ? 0.0 : (p == 0 ? a[(size_t)row * M + c] : Ub[at * SP + c]);
-            const bool act0 = act;
-            if (nb == NB) lu8_panel_steps<true>(v, act, mypos, fail_code, fail_col, j0, nb, row, lane, w, cslot, crow, cnt, sc);
-            else lu8_panel_steps<false>(v, act, mypos, fail_code, fail_col, j0, nb, row, lane, w, cslot, crow, cnt, sc);
-            PHASE_MARK(q1t);
-            PHASE_ADD_T(0, q0t, q1t, 0);
-            __syncthreads();   // the other waves are done with the previous Lb and list
-            if (act0) {
+            for (int r = 0; r < 4; ++r)
 #pragma unroll
-                for (int c = 0; c < NB; ++c) {
-                    Lb[row * LP + c] = v[c];
-                    if (act && c < nb) a[(size_t)row * M + j0 + c] = v[c];
+                for (int c = 0; c < NB; ++c) v[r][c] = act[r] ? NX[(cur * 256 + 4 * lane + r) * P + c] : 0.0;
+            bool act0[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) act0[r] = act[r];
+            lw_panel_steps(v, act, fail_code, fail_col, j0, nb, lane, PIV + cur * NB, PROW);
+            // publish the panel rows and the list of rows left (row order)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (act0[r]) {
+#pragma unroll
+                    for (int c = 0; c < NB; ++c) LB[(cur * 256 + 4 * lane + r) * P + c] = v[r][c];
                 }
-            }
-            if (mypos >= j0 && mypos < j0 + nb) piv[mypos - j0] = row;
-            const unsigned long long am = __ballot(act);
-            if (lane == 0) wcnt[w] = __popcll(am);
-            __syncthreads();
-            int base = 0;
+            int pos = 0;
 #pragma unroll
-            for (int q = 0; q < LU8_NP; ++q) base += q < w ? wcnt[q] : 0;
-            if (act) {
-                const int at2 = base + __popcll(am & ((1ull << lane) - 1ull));
-                list[at2] = row;
-                lpos[row] = at2;
+            for (int r = 0; r < 4; ++r) {
+                const unsigned long long bal = __ballot(act[r]);
+                pos += __builtin_amdgcn_mbcnt_hi((unsigned)(bal >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
             }
-        } else {
-            // ---------------- the previous panel's update right of panel p
-            if (p > 0) {
-                const int h2 = ph2, w2p = ph2, pc0 = pj0 + pnb;
-                const int tc_n = (w2p + 31) / 32, tr_n = (h2 + 31) / 32, tcr = tc_n - 1, nrest = tr_n * tcr;
-                double* a2 = a + pc0;
-                const double* u12 = out + (size_t)pj0 * M + pc0;   // rows of U12 (final), leading dimension M
-                // the C tile of a tile (and its rows); the U12 operands are read when the
-                // tile is multiplied (they stay in L2)
-                auto load_t = [&](int s, v4d (&c)[2][2], int (&crw)[2][4]) {
-                    const int tr = (s / tcr) * 32, tc = (1 + s % tcr) * 32;
 #pragma unroll
-                    for (int x = 0; x < 2; ++x)
+            for (int r = 0; r < 4; ++r)
+                if (act[r]) LIST[cur * 256 + pos++] = 4 * lane + r;
+        } else if (p > 0) {
+            // ---------------- panel q = p-1 applied right of panel p; its factor rows
+            const int q = p - 1, qc = q & 1, j0q = q * NB;
+            const int hq = M - j0q - NB;                 // rows left after panel q
+            const int cs0 = j0 + NB;                     // first column right of panel p
+            const int nsl = cs0 < M ? (M - cs0 + NB - 1) / NB : 0;
+            const int* pvq = PIV + qc * NB;
+            const int* lsq = LIST + qc * 256;
+            const double* lbq = LB + (size_t)qc * 256 * P;
+            double* nxd = NX + (size_t)nxt * 256 * P;   // columns of panel p+1
+            for (int s = w - 1; s < nsl; s += LW_HW) {
+                const int col = cs0 + s * NB + cc;
+                const bool cok = col < M;
+                double bo[4];
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) bo[kk] = cok ? a[(size_t)pvq[4 * kk + g] * M + col] : 0.0;
+                v4d u = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) u = mfma4(TB[cc * P + 4 * kk + g], bo[kk], u);
+#pragma unroll
+                for (int vv = 0; vv < 4; ++vv)
+                    if (cok) out[(size_t)(j0q + g + 4 * vv) * M + col] = u[vv];
+                // A22 -= L21 U12 over the rows left, four 16-row tiles per batch
+                for (int tb = 0; tb < hq; tb += 64) {
+                    v4d cv[4];
+                    int rw[4][4];
+#pragma unroll
+                    for (int x = 0; x < 4; ++x)
 #pragma unroll
                         for (int vv = 0; vv < 4; ++vv) {
-                            const int idx = tr + 16 * x + g + 4 * vv;
-                            crw[x][vv] = idx < h2 ? list[idx] : -1;
+                            const int idx = tb + 16 * x + g + 4 * vv;
+                            rw[x][vv] = idx < hq ? lsq[idx] : -1;
                         }
 #pragma unroll
-                    for (int x = 0; x < 2; ++x)
+                    for (int x = 0; x < 4; ++x)
 #pragma unroll
-                        for (int y = 0; y < 2; ++y) {
-                            const int col = tc + 16 * y + (lane & 15);
+                        for (int vv = 0; vv < 4; ++vv)
+                            cv[x][vv] = (rw[x][vv] >= 0 && cok) ? a[(uint32_t)(rw[x][vv] * M + col)] : 0.0;
 #pragma unroll
-                            for (int vv = 0; vv < 4; ++vv)
-                                c[x][y][vv] = (crw[x][vv] >= 0 && col < w2p) ? a2[(uint32_t)(crw[x][vv] * M + col)] : 0.0;
-                        }
-                };
-                auto mul_t = [&](int s, v4d (&c)[2][2], const int (&crw)[2][4]) {
-                    const int tr = (s / tcr) * 32, tc = (1 + s % tcr) * 32;
-                    double bo[KS][2];
+                    for (int x = 0; x < 4; ++x) {
+                        const int ai = tb + 16 * x + cc;
+                        const int ar = ai < hq ? lsq[ai] : -1;
 #pragma unroll
-                    for (int kk = 0; kk < KS; ++kk)
-#pragma unroll
-                        for (int y = 0; y < 2; ++y) {
-                            const int col = tc + 16 * y + (lane & 15);
-                            bo[kk][y] = col < w2p ? u12[(uint32_t)((4 * kk + g) * M + col)] : 0.0;
-                        }
-                    int arw[2];
-#pragma unroll
-                    for (int x = 0; x < 2; ++x) {
-                        const int idx = tr + 16 * x + (lane & 15);
-                        arw[x] = idx < h2 ? list[idx] : -1;
+                        for (int kk = 0; kk < 4; ++kk)
+                            cv[x] = mfma4(ar >= 0 ? -lbq[ar * P + 4 * kk + g] : 0.0, u[kk], cv[x]);
                     }
 #pragma unroll
-                    for (int kk = 0; kk < KS; ++kk) {
-                        double av[2];
+                    for (int x = 0; x < 4; ++x)
 #pragma unroll
-                        for (int x = 0; x < 2; ++x) av[x] = arw[x] >= 0 ? -Lb[arw[x] * LP + 4 * kk + g] : 0.0;
-#pragma unroll
-                        for (int x = 0; x < 2; ++x)
-#pragma unroll
-                            for (int y = 0; y < 2; ++y) c[x][y] = mfma4(av[x], bo[kk][y], c[x][y]);
-                    }
-#pragma unroll
-                    for (int x = 0; x < 2; ++x)
-#pragma unroll
-                        for (int y = 0; y < 2; ++y) {
-                            const int col = tc + 16 * y + (lane & 15);
-#pragma unroll
-                            for (int vv = 0; vv < 4; ++vv)
-                                if (crw[x][vv] >= 0 && col < w2p) a2[(uint32_t)(crw[x][vv] * M + col)] = c[x][y][vv];
-                        }
-                };
-                constexpr int UW = NW - LU8_NP;   // updating waves
-                // one tile at a time: a second tile in flight would not fit the
-                // registers of an eight-wave group, and these waves are not on the
-                // critical path (they finish well within the panel)
-                v4d c0[2][2];
-                int q0[2][4];
-                for (int s = w - LU8_NP; s < nrest; s += UW) {
-                    load_t(s, c0, q0);
-                    mul_t(s, c0, q0);
+                        for (int vv = 0; vv < 4; ++vv)
+                            if (rw[x][vv] >= 0 && cok) {
+                                if (s == 0) nxd[rw[x][vv] * P + cc] = cv[x][vv];
+                                else a[(uint32_t)(rw[x][vv] * M + col)] = cv[x][vv];
+                            }
                 }
             }
-            PHASE_MARK(q2t);
-            PHASE_ADD_T(1, q0t, q2t, 256);
-            __syncthreads();   // pairs with the owners' barrier after their panel
-            __syncthreads();   // pairs with the owners' barrier around the list counts
-        }
-        __syncthreads();
-        PHASE_MARK(q3t);
-        PHASE_ADD_T(2, q0t, q3t, 0);
-        // ---------------- the pivot rows, read once from the working copy: the
-        // multipliers left of the panel go to the factors, A12 to Ub
-        {
-            constexpr int RW = NB / NW, CL = 4;   // 4 rows per wave, M <= 256 columns
-            double val[RW][CL];
-#pragma unroll
-            for (int q = 0; q < RW; ++q) {
-                const int rr = w + q * NW;
-                const int pr = rr < nb ? piv[rr] : 0;
-#pragma unroll
-                for (int u = 0; u < CL; ++u) {
-                    const int c = lane + 64 * u;
-                    val[q][u] = (rr < nb && c < M && (c < j0 || c >= j0 + nb)) ? a[(size_t)pr * M + c] : 0.0;
-                }
-            }
-#pragma unroll
-            for (int q = 0; q < RW; ++q) {
-                const int rr = w + q * NW;
-                if (rr < nb) {
-                    const int pr = piv[rr];
-#pragma unroll
-                    for (int u = 0; u < CL; ++u) {
-                        const int c = lane + 64 * u;
-                        if (c < j0) out[(size_t)(j0 + rr) * M + c] = val[q][u];
-                        else if (c < j0 + nb) out[(size_t)(j0 + rr) * M + c] = Lb[pr * LP + c - j0];
-                        else if (c < M) Ub[rr * UP + c - j0 - nb] = val[q][u];
-                    }
+            // factor rows of panel q left of the slabs (multipliers from the working
+            // copy, the panel from LDS, the next panel's U12), the pivot order, and
+            // the multipliers of the rows left back to the working copy
+            const int W1 = min(M, j0q + NB + nb);
+            const int n1 = NB * W1, n2 = hq * NB;
+            for (int x = (w - 1) * 64 + lane; x < n1 + n2; x += LW_HW * 64) {
+                if (x < n1) {
+                    const int rr = x / W1, c = x - rr * W1;
+                    const int prow = pvq[rr];
+                    double val;
+                    if (c < j0q) val = a[(size_t)prow * M + c];
+                    else if (c < j0q + NB) val = lbq[prow * P + c - j0q];
+                    else val = UN[rr * P + c - j0q - NB];
+                    out[(size_t)(j0q + rr) * M + c] = val;
+                    if (c == 0) perm[j0q + rr] = prow;
+                } else {
+                    const int y = x - n1, ri = y / NB, c = y - ri * NB;
+                    const int row = lsq[ri];
+                    a[(size_t)row * M + j0q + c] = lbq[row * P + c];
                 }
             }
         }
+        __syncthreads();   // panel p published; panel p-1 applied
         if (w2 <= 0) break;
-        __syncthreads();
-        PHASE_MARK(q4t);
-        PHASE_ADD_T(3, q3t, q4t, 0);
-        // ---------------- inv(L11) and U12 = inv(L11) A12 (as in k_getrf)
-        if (w == 0 && lane < NB) {
-            const int half = lane / 16, jc = lane % 16, o = half * 16;
-            double x[16];
-#pragma unroll
-            for (int rr = 0; rr < 16; ++rr) {
-                double sacc = (rr == jc) ? 1.0 : 0.0;
-                const double* lr = Lb + piv[o + rr] * LP + o;
-#pragma unroll
-                for (int c = 0; c < rr; ++c) sacc = fma(-lr[c], x[c], sacc);
-                x[rr] = rr >= jc ? sacc : 0.0;
-            }
-#pragma unroll
-            for (int rr = 0; rr < 16; ++rr) Tb[(o + rr) * TP + o + jc] = x[rr];
-#pragma unroll
-            for (int rr = 0; rr < 16; ++rr) Tb[rr * TP + 16 + jc] = 0.0;
-        }
-        __syncthreads();
+        const int nb2 = min(NB, w2);
+        // ---------------- inv(L11) of panel p and U12 of the columns of panel p+1
         if (w == 0) {
+            const int* pv = PIV + cur * NB;
+            const double* lb = LB + (size_t)cur * 256 * P;
+            if (lane < NB) {
+                const int jc = lane;
+                double x[NB];
+#pragma unroll
+                for (int rr = 0; rr < NB; ++rr) {
+                    const double* lr = lb + pv[rr] * P;
+                    double s4[4] = {rr == jc ? 1.0 : 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                    for (int c = 0; c < rr; ++c) s4[c & 3] = fma(-lr[c], x[c], s4[c & 3]);
+                    x[rr] = rr >= jc ? (s4[0] + s4[1]) + (s4[2] + s4[3]) : 0.0;
+                }
+#pragma unroll
+                for (int rr = 0; rr < NB; ++rr) TB[rr * P + jc] = x[rr];
+            }
+            wave_lds_sync();
+            const double* nxn = NX + (size_t)nxt * 256 * P;
             v4d acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int kk = 0; kk < 4; ++kk)
-                acc = mfma4(Lb[piv[16 + (lane & 15)] * LP + 4 * kk + g], Tb[(4 * kk + g) * TP + (lane & 15)], acc);
-            double* wt = crow;   // 16 x 16 scratch
+                acc = mfma4(TB[cc * P + 4 * kk + g], cc < nb2 ? nxn[pv[4 * kk + g] * P + cc] : 0.0, acc);
 #pragma unroll
-            for (int vv = 0; vv < 4; ++vv) wt[(g + 4 * vv) * 16 + (lane & 15)] = acc[vv];
-            wave_lds_sync();
-            v4d acc2 = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-            for (int kk = 0; kk < 4; ++kk)
-                acc2 = mfma4(-Tb[(16 + (lane & 15)) * TP + 16 + 4 * kk + g], wt[(4 * kk + g) * 16 + (lane & 15)], acc2);
-#pragma unroll
-            for (int vv = 0; vv < 4; ++vv) Tb[(16 + g + 4 * vv) * TP + (lane & 15)] = acc2[vv];
+            for (int vv = 0; vv < 4; ++vv) UN[(g + 4 * vv) * P + cc] = acc[vv];
         }
         __syncthreads();
-        for (int cs = w * 16; cs < w2; cs += NW * 16) {
-            const int col = cs + (lane & 15);
-            double bop[KS];
-#pragma unroll
-            for (int kk = 0; kk < KS; ++kk) bop[kk] = col < w2 ? Ub[(4 * kk + g) * UP + col] : 0.0;
-#pragma unroll
-            for (int x = 0; x < NB / 16; ++x) {
-                v4d acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                for (int kk = 0; kk < KS; ++kk) acc = mfma4(Tb[(16 * x + (lane & 15)) * TP + 4 * kk + g], bop[kk], acc);
+        // ---------------- the columns of panel p+1 of the rows left: -= L21 U12 (all waves)
+        {
+            const double* lb = LB + (size_t)cur * 256 * P;
+            const int* ls = LIST + cur * 256;
+            double* nxn = NX + (size_t)nxt * 256 * P;
+            for (int tb = w * 16; tb < w2; tb += 8 * 16) {
+                int rw[4];
 #pragma unroll
                 for (int vv = 0; vv < 4; ++vv) {
-                    const int rr = 16 * x + g + 4 * vv;
-                    Ub[rr * UP + col] = acc[vv];
-                    if (col < w2) out[(size_t)(j0 + rr) * M + j0 + nb + col] = acc[vv];
+                    const int idx = tb + g + 4 * vv;
+                    rw[vv] = idx < w2 ? ls[idx] : -1;
                 }
+                v4d cv;
+#pragma unroll
+                for (int vv = 0; vv < 4; ++vv) cv[vv] = rw[vv] >= 0 ? nxn[rw[vv] * P + cc] : 0.0;
+                const int ai = tb + cc;
+                const int ar = ai < w2 ? ls[ai] : -1;
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk)
+                    cv = mfma4(ar >= 0 ? -lb[ar * P + 4 * kk + g] : 0.0, UN[(4 * kk + g) * P + cc], cv);
+#pragma unroll
+                for (int vv = 0; vv < 4; ++vv)
+                    if (rw[vv] >= 0) nxn[rw[vv] * P + cc] = cv[vv];
             }
         }
         __syncthreads();
-        PHASE_MARK(q5t);
-        PHASE_ADD_T(4, q4t, q5t, 0);
-        // ---------------- the next panel's columns of A22 (tile column 0) on all
-        // waves, handed to the row owners through LDS (list order, over Ub)
-        {
-            const int h2 = w2, tr_n = (h2 + 31) / 32;
-            double* a2 = a + j0 + nb;
-            const int tr = w * 32;   // at most 7 row tiles for 8 waves
-            v4d acc[2][2];
-            int crw[2][4];
-            if (tr < h2) {
-#pragma unroll
-                for (int x = 0; x < 2; ++x)
-#pragma unroll
-                    for (int vv = 0; vv < 4; ++vv) {
-                        const int idx = tr + 16 * x + g + 4 * vv;
-                        crw[x][vv] = idx < h2 ? list[idx] : -1;
-                    }
-#pragma unroll
-                for (int x = 0; x < 2; ++x)
-#pragma unroll
-                    for (int y = 0; y < 2; ++y) {
-                        const int col = 16 * y + (lane & 15);
-#pragma unroll
-                        for (int vv = 0; vv < 4; ++vv)
-                            acc[x][y][vv] = (crw[x][vv] >= 0 && col < w2) ? a2[(size_t)crw[x][vv] * M + col] : 0.0;
-                    }
-                int arw[2];
-#pragma unroll
-                for (int x = 0; x < 2; ++x) {
-                    const int idx = tr + 16 * x + (lane & 15);
-                    arw[x] = idx < h2 ? list[idx] : -1;
-                }
-#pragma unroll
-                for (int kk = 0; kk < KS; ++kk) {
-                    double av[2], bv[2];
-#pragma unroll
-                    for (int x = 0; x < 2; ++x) av[x] = arw[x] >= 0 ? -Lb[arw[x] * LP + 4 * kk + g] : 0.0;
-#pragma unroll
-                    for (int y = 0; y < 2; ++y) {
-                        const int col = 16 * y + (lane & 15);
-                        bv[y] = col < w2 ? Ub[(4 * kk + g) * UP + col] : 0.0;
-                    }
-#pragma unroll
-                    for (int x = 0; x < 2; ++x)
-#pragma unroll
-                        for (int y = 0; y < 2; ++y) acc[x][y] = mfma4(av[x], bv[y], acc[x][y]);
-                }
-            }
-            (void)tr_n;
-            __syncthreads();   // every read of U12 in Ub done
-            if (tr < h2) {
-#pragma unroll
-                for (int x = 0; x < 2; ++x)
-#pragma unroll
-                    for (int y = 0; y < 2; ++y)
-#pragma unroll
-                        for (int vv = 0; vv < 4; ++vv) {
-                            const int idx = tr + 16 * x + g + 4 * vv;
-                            if (idx < h2) Ub[idx * SP + 16 * y + (lane & 15)] = acc[x][y][vv];
-                        }
-            }
-            __syncthreads();
+    }
+    // ---------------- factor rows of the last panel, the failure report
+    {
+        const int j0 = p * NB, nb = M - j0, cur = p & 1;
+        const int* pv = PIV + cur * NB;
+        const double* lb = LB + (size_t)cur * 256 * P;
+        for (int x = tid; x < nb * M; x += LW_NT) {
+            const int rr = x / M, c = x - rr * M;
+            const int prow = pv[rr];
+            out[(size_t)(j0 + rr) * M + c] = c < j0 ? a[(size_t)prow * M + c] : lb[prow * P + c - j0];
+            if (c == 0) perm[j0 + rr] = prow;
         }
-        PHASE_MARK(q6t);
-        PHASE_ADD_T(5, q5t, q6t, 0);
-        pj0 = j0; pnb = nb; ph2 = w2;
     }
-    if (owner) {
-        int* perm = L.perm + (size_t)i * M;
-        if (mypos >= 0) perm[mypos] = row;
-        if (lane0 == 0 && fail_code != 0) report_status(ka.status, L.level, i, fail_col, fail_code);
-    }
+    if (w == 0 && lane0 == 0 && fail_code != 0) report_status(ka.status, L.level, i, fail_col, fail_code);
 }
 
 // Preparation of the factors of every D_i factored at this step for the
@@ -2412,14 +2320,14 @@ hipError_t launch_recover(const KArgs& ka, hipStream_t s) {
 static bool getrf_small(int M) { return M <= 256; }
 
 size_t getrf_lds_bytes(int M) {
-    return getrf_small(M) ? lu8_lds_layout(M).total : lu_lds_layout(M, 512, 16).total;
+    return getrf_small(M) ? lw_lds_layout().total : lu_lds_layout(M, 512, 16).total;
 }
 
 hipError_t launch_getrf(const KArgs& ka, hipStream_t s) {
     const int M = ka.L.M;
     const size_t lds = getrf_lds_bytes(M);
     dim3 grid(ka.nc);
-    if (getrf_small(M)) hipLaunchKernelGGL(k_getrf8, grid, dim3(LU8_NT), lds, s, ka);
+    if (getrf_small(M)) hipLaunchKernelGGL(k_getrf_pw, grid, dim3(LW_NT), lds, s, ka);
     else hipLaunchKernelGGL((k_getrf<512, 16>), grid, dim3(512), lds, s, ka);
     return hipGetLastError();
 }
@@ -2541,7 +2449,7 @@ hipError_t read_phase_times(unsigned long long* out) {
 hipError_t configure_kernels() {
     const int lds_max = 160 * 1024;
     hipError_t err;
-    const void* getrf_kernels[] = {(const void*)k_getrf8, (const void*)k_getrf<512, 16>};
+    const void* getrf_kernels[] = {(const void*)k_getrf_pw, (const void*)k_getrf<512, 16>};
     for (const void* f : getrf_kernels) {
         err = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_max);
         if (err != hipSuccess) return err;
