@@ -2347,16 +2347,16 @@ static void launch_getrs_w(const KArgs& ka, hipStream_t s) {
     hipLaunchKernelGGL((k_getrs_w<NBLK, NT16, WPB>), dim3(cdiv(nslab * ka.nc, WPB)), dim3(64 * WPB), 0, s, ka, nslab);
 }
 
-template <int NBLK, int NT16>
+template <int NBLK, int NT16, int WPB = 4>
 static void launch_getrs_s(const KArgs& ka, hipStream_t s) {
-    constexpr int WPB = 4;
     const int nslab = cdiv(2 * ka.L.M, 16 * NT16), wpc = cdiv(nslab, WPB);
     hipLaunchKernelGGL((k_getrs_s<NBLK, NT16, WPB>), dim3(wpc * ka.nc), dim3(64 * WPB), 0, s, ka, nslab, wpc);
 }
 
-// M <= 256: slabs of 32 columns (64 for M <= 64) held in one wave's
-// accumulators, four slabs of one chunk per workgroup sharing the factor
-// blocks through LDS; above: the workgroup slab kernel.
+// M <= 256: slabs of 32 columns (64 for M <= 64; 16 above M = 128, so that
+// two waves fit on a SIMD) held in one wave's accumulators, four slabs of
+// one chunk per workgroup (eight above M = 128) sharing the factor blocks
+// through LDS; above: the workgroup slab kernel.
 hipError_t launch_getrs(const KArgs& ka, hipStream_t s) {
     const int M = ka.L.M;
     if (M <= 256) {
@@ -2364,7 +2364,7 @@ hipError_t launch_getrs(const KArgs& ka, hipStream_t s) {
         if (nblk <= 1) launch_getrs_s<1, 4>(ka, s);
         else if (nblk <= 2) launch_getrs_s<2, 4>(ka, s);
         else if (nblk <= 4) launch_getrs_s<4, 2>(ka, s);
-        else launch_getrs_s<8, 2>(ka, s);
+        else launch_getrs_s<8, 1, 8>(ka, s);   // 16-column slabs: two waves per SIMD
         return hipGetLastError();
     }
     const int sw = slab_width(M);
