@@ -52,42 +52,6 @@ __device__ __forceinline__ double readlane_d(double v, int l) {
                             __builtin_amdgcn_readlane(__double2loint(v), l));
 }
 
-// DPP move that leaves the rows outside ROWMASK unchanged.
-template <int CTRL, int ROWMASK>
-__device__ __forceinline__ double dpp_upd(double v) {
-    const int lo = __builtin_amdgcn_update_dpp(__double2loint(v), __double2loint(v), CTRL, ROWMASK, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(__double2hiint(v), __double2hiint(v), CTRL, ROWMASK, 0xf, false);
-    return __hiloint2double(hi, lo);
-}
-
-// Maximum over the 64 lanes (NaN inputs never win), returned as a uniform
-// value: row reduction by row permutations, then row_bcast15 / row_bcast31
-// carry the row maxima up to lane 63.
-__device__ __forceinline__ double wave_max(double v) {
-    v = fmax(v, dpp_mov<0xB1>(v));         // quad_perm [1,0,3,2]
-    v = fmax(v, dpp_mov<0x4E>(v));         // quad_perm [2,3,0,1]
-    v = fmax(v, dpp_mov<0x141>(v));        // row_half_mirror
-    v = fmax(v, dpp_mov<0x140>(v));        // row_mirror
-    v = fmax(v, dpp_upd<0x142, 0xa>(v));   // row_bcast15 into rows 1 and 3
-    v = fmax(v, dpp_upd<0x143, 0xc>(v));   // row_bcast31 into rows 2 and 3
-    return readlane_d(v, 63);
-}
-
-template <int CTRL>
-__device__ __forceinline__ int dpp_mov_i(int v) {
-    return __builtin_amdgcn_mov_dpp(v, CTRL, 0xf, 0xf, false);
-}
-
-// Minimum over the 64 lanes, returned to every lane.
-__device__ __forceinline__ int wave_min_int(int v) {
-    v = min(v, dpp_mov_i<0xB1>(v));
-    v = min(v, dpp_mov_i<0x4E>(v));
-    v = min(v, dpp_mov_i<0x141>(v));
-    v = min(v, dpp_mov_i<0x140>(v));
-    return min(min(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
-               min(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
-}
-
 // Maximum of an unsigned 32-bit value over the 64 lanes, uniform result:
 // one DPP-modified v_max_u32 per stage.
 __device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
@@ -1503,14 +1467,14 @@ __global__ __launch_bounds__(256) void k_getrs(const KArgs ka) {
                         ownb);
 }
 
-// ------------------------------------------------------------------ triangular solves, one wave per slab
+// ------------------------------------------------------------------ triangular solves, one slab per wave
 //
 // For M <= 256: X := U^{-1} L^{-1} (P X) on a slab of 16*NT16 columns of
-// W_i, held entirely in one wave's MFMA accumulators; no LDS and no
-// barrier.  With the scaled off-diagonal blocks of k_diag_prep a sweep
-// subtracts Lt_{b',b} w_b (forward, b' > b) or Ut_{b',b} w_b (backward,
-// b' < b) with the unsolved block w_b, and the diagonal inverses are applied
-// to all blocks after each sweep.
+// W_i, held entirely in one wave's MFMA accumulators.  With the scaled
+// off-diagonal blocks of k_diag_prep a sweep subtracts Lt_{b',b} w_b
+// (forward, b' > b) or Ut_{b',b} w_b (backward, b' < b) with the unsolved
+// block w_b, and the diagonal inverses are applied to all blocks after each
+// sweep.
 //
 // Register layout: in lane l (g = l >> 4, j = l & 15) accumulator register
 // v of row tile tr of block b holds row 32b + 8g + 4tr + v, column j of
@@ -1539,28 +1503,6 @@ __host__ __device__ constexpr int trsm_pair(int p, bool fwd, bool want_src) {
     return 0;
 }
 
-// Left operand: rows of block bp (permuted per output tile), columns
-// 32 b + 8 g .. + 7, scaled by sgn; zero outside the matrix.
-__device__ __forceinline__ void trsmw_load(const double* __restrict__ src, int ld, int M, int bp, int b, int lane,
-                                           double sgn, double (&o)[2][8]) {
-    const int g = lane >> 4, i16 = lane & 15;
-    const int c0 = b * DB + g * 8;
-#pragma unroll
-    for (int tr = 0; tr < 2; ++tr) {
-        const int row = bp * DB + 8 * (i16 & 3) + 4 * tr + (i16 >> 2);
-        if (row < M && c0 + 7 < M && (ld & 3) == 0) {
-            const double4* p4 = (const double4*)(src + (uint32_t)(row * ld + c0));
-            const double4 v0 = p4[0], v1 = p4[1];
-            o[tr][0] = sgn * v0.x; o[tr][1] = sgn * v0.y; o[tr][2] = sgn * v0.z; o[tr][3] = sgn * v0.w;
-            o[tr][4] = sgn * v1.x; o[tr][5] = sgn * v1.y; o[tr][6] = sgn * v1.z; o[tr][7] = sgn * v1.w;
-        } else {
-#pragma unroll
-            for (int kk = 0; kk < 8; ++kk)
-                o[tr][kk] = (row < M && c0 + kk < M) ? sgn * src[(uint32_t)(row * ld + c0 + kk)] : 0.0;
-        }
-    }
-}
-
 // x_bp -= T_{bp,b} x_b (the operand already negated)
 template <int NBLK, int NT16, int B, int BP>
 __device__ __forceinline__ void trsmw_update(v4d (&x)[NBLK][2][NT16], const double (&o)[2][8]) {
@@ -1573,134 +1515,11 @@ __device__ __forceinline__ void trsmw_update(v4d (&x)[NBLK][2][NT16], const doub
                 x[BP][tr][nt] = mfma4(o[tr][kk], x[B][kk >> 2][nt][kk & 3], x[BP][tr][nt]);
 }
 
-// One sweep over the block pairs from P on, operands one pair ahead.
-template <int NBLK, int NT16, bool FWD, int P>
-__device__ __forceinline__ void trsmw_sweep(v4d (&x)[NBLK][2][NT16], const double* __restrict__ lu, int M, int lane,
-                                            double (&cur)[2][8], double (&nxt)[2][8]) {
-    constexpr int NP = trsm_npairs<NBLK>();
-    if constexpr (P < NP) {
-        constexpr int B = trsm_pair<NBLK>(P, FWD, true), BP = trsm_pair<NBLK>(P, FWD, false);
-        if constexpr (P + 1 < NP)
-            trsmw_load(lu, M, M, trsm_pair<NBLK>(P + 1, FWD, false), trsm_pair<NBLK>(P + 1, FWD, true), lane, -1.0,
-                       nxt);
-        trsmw_update<NBLK, NT16, B, BP>(x, cur);
-        trsmw_sweep<NBLK, NT16, FWD, P + 1>(x, lu, M, lane, nxt, cur);
-    }
-}
-
-// x_b := inv(T_bb) x_b for every block, the next block's inverse loaded
-// ahead (zero past the last block, whose x is zero).
-template <int NBLK, int NT16, int B>
-__device__ __forceinline__ void trsmw_diag(v4d (&x)[NBLK][2][NT16], const double* __restrict__ di, int nblk, int dir,
-                                           int lane, double (&cur)[2][8], double (&nxt)[2][8]) {
-    if constexpr (B < NBLK) {
-        if constexpr (B + 1 < NBLK)
-            trsmw_load(di + (size_t)(B + 1 < nblk ? B + 1 : 0) * DI_STRIDE + (dir ? DB * DB : 0), DB,
-                       B + 1 < nblk ? DB : 0, 0, 0, lane, 1.0, nxt);
-        v4d nw[2][NT16];
-#pragma unroll
-        for (int tr = 0; tr < 2; ++tr)
-#pragma unroll
-            for (int nt = 0; nt < NT16; ++nt) nw[tr][nt] = (v4d){0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int kk = 0; kk < 8; ++kk)
-#pragma unroll
-            for (int tr = 0; tr < 2; ++tr)
-#pragma unroll
-                for (int nt = 0; nt < NT16; ++nt) nw[tr][nt] = mfma4(cur[tr][kk], x[B][kk >> 2][nt][kk & 3], nw[tr][nt]);
-#pragma unroll
-        for (int tr = 0; tr < 2; ++tr)
-#pragma unroll
-            for (int nt = 0; nt < NT16; ++nt) x[B][tr][nt] = nw[tr][nt];
-        trsmw_diag<NBLK, NT16, B + 1>(x, di, nblk, dir, lane, nxt, cur);
-    }
-}
-
-// RHS = W_i = [C_i | -B_i Y_{i-1}] of the chunk's row at step t; grid =
-// nslab slabs x chunks in one dimension, one wave each, XCD-aware order so
-// that the slabs of one chunk share an L2.
-template <int NBLK, int NT16, int WPB>
-__global__ __launch_bounds__(64 * WPB) void k_getrs_w(const KArgs ka, int nslab) {
-    const Level& L = ka.L;
-    const int M = L.M;
-    // WPB consecutive slabs per workgroup: the waves of one CU mostly read the
-    // same factor blocks at about the same time (shared L1)
-    const int wid = xcd_logical_id(blockIdx.x, gridDim.x) * WPB + (int)(threadIdx.x >> 6);
-    if (wid >= nslab * ka.nc) return;
-    const int k = ka.c0 + wid / nslab, slab = wid % nslab;
-    const int r = chunk_first(L, k), e = chunk_last(L, k), t = ka.step;
-    if (t > e - r) return;
-    const int i = r + t;
-    constexpr int SW = 16 * NT16;
-    const int c0 = slab * SW;
-    const int e_hi = (i != L.N - 1) ? M : 0;          // E_i columns [0, e_hi)
-    const int y_hi = (k > 0) ? 2 * M : M;             // Y_i columns [M, y_hi)
-    if (!(c0 < e_hi || (c0 < y_hi && c0 + SW > M))) return;
-    const int lane = threadIdx.x & 63, g = lane >> 4, j = lane & 15;
-    const int nblk = (M + DB - 1) / DB;
-    const double* lu = L.LU + (size_t)i * M * M;
-    const double* di = L.DI + (size_t)i * nblk * DI_STRIDE;
-    const int* perm = L.perm + (size_t)i * M;
-    double* X = L.W + (size_t)i * M * 2 * M;
-    const int ld = 2 * M;
-    v4d x[NBLK][2][NT16];
-    int prow[NBLK][2][4];
-#pragma unroll
-    for (int b = 0; b < NBLK; ++b)
-#pragma unroll
-        for (int tr = 0; tr < 2; ++tr)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int row = b * DB + 8 * g + 4 * tr + v;
-                prow[b][tr][v] = row < M ? perm[row] : -1;
-            }
-#pragma unroll
-    for (int b = 0; b < NBLK; ++b)
-#pragma unroll
-        for (int tr = 0; tr < 2; ++tr)
-#pragma unroll
-            for (int nt = 0; nt < NT16; ++nt) {
-                const int col = c0 + 16 * nt + j;
-                const bool cv = col < e_hi || (col >= M && col < y_hi);
-#pragma unroll
-                for (int v = 0; v < 4; ++v)
-                    x[b][tr][nt][v] = (cv && prow[b][tr][v] >= 0) ? X[(uint32_t)(prow[b][tr][v] * ld + col)] : 0.0;
-            }
-    double o0[2][8], o1[2][8];
-    if constexpr (NBLK > 1) {
-        trsmw_load(lu, M, M, trsm_pair<NBLK>(0, true, false), trsm_pair<NBLK>(0, true, true), lane, -1.0, o0);
-        trsmw_sweep<NBLK, NT16, true, 0>(x, lu, M, lane, o0, o1);
-    }
-    trsmw_load(di, DB, DB, 0, 0, lane, 1.0, o0);
-    trsmw_diag<NBLK, NT16, 0>(x, di, nblk, 0, lane, o0, o1);
-    if constexpr (NBLK > 1) {
-        trsmw_load(lu, M, M, trsm_pair<NBLK>(0, false, false), trsm_pair<NBLK>(0, false, true), lane, -1.0, o0);
-        trsmw_sweep<NBLK, NT16, false, 0>(x, lu, M, lane, o0, o1);
-    }
-    trsmw_load(di + DB * DB, DB, DB, 0, 0, lane, 1.0, o0);
-    trsmw_diag<NBLK, NT16, 0>(x, di, nblk, 1, lane, o0, o1);
-#pragma unroll
-    for (int b = 0; b < NBLK; ++b)
-#pragma unroll
-        for (int tr = 0; tr < 2; ++tr)
-#pragma unroll
-            for (int nt = 0; nt < NT16; ++nt) {
-                const int col = c0 + 16 * nt + j;
-                const bool cv = col < e_hi || (col >= M && col < y_hi);
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int row = b * DB + 8 * g + 4 * tr + v;
-                    if (cv && row < M) X[(uint32_t)(row * ld + col)] = x[b][tr][nt][v];
-                }
-            }
-}
-
 // ------------------------------------------------------------------ triangular solves, operands shared in LDS
 //
-// As k_getrs_w (same register layout of the right-hand side, same scaled
-// blocks), but a workgroup of WPB waves covers WPB consecutive slabs of one
-// chunk and the 32 x 32 factor blocks go through LDS once per workgroup
-// instead of once per wave: the blocks of the whole sequence (forward block
+// A workgroup of WPB waves covers WPB consecutive slabs of one chunk (the
+// register layout above) and the 32 x 32 factor blocks go through LDS once
+// per workgroup instead of once per wave: the blocks of the whole sequence (forward block
 // pairs, inverses of the diagonal blocks of L, backward pairs, inverses of
 // the diagonal blocks of U) stream through a ring of four LDS slots, each
 // thread loading one 32-byte piece two blocks ahead, with one barrier per
@@ -2339,13 +2158,6 @@ hipError_t launch_diag_inv(const KArgs& ka, hipStream_t s) {
 }
 
 static int slab_width(int M) { return M <= 256 ? 32 : 16; }
-
-template <int NBLK, int NT16>
-static void launch_getrs_w(const KArgs& ka, hipStream_t s) {
-    constexpr int WPB = 4;
-    const int nslab = cdiv(2 * ka.L.M, 16 * NT16);
-    hipLaunchKernelGGL((k_getrs_w<NBLK, NT16, WPB>), dim3(cdiv(nslab * ka.nc, WPB)), dim3(64 * WPB), 0, s, ka, nslab);
-}
 
 template <int NBLK, int NT16, int WPB = 4>
 static void launch_getrs_s(const KArgs& ka, hipStream_t s) {
