@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--depth", type=int, default=None)
     ap.add_argument("--coupling-rows", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-breakdown", action="store_true",
+                    help="skip the factor-only / solve-only timings and the one-subsystem (TA) run")
     ap.add_argument("--cpu-sample-rows", type=int, default=None)
     ap.add_argument("--roofline-class", default="auto")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
@@ -105,6 +107,25 @@ class Runner:
         self.sh = ctypes.c_void_p(self.stream.cuda_stream)
         self.plans = []
 
+    def use_stream(self, stream):
+        self.stream = stream
+        self.sh = self.ct.c_void_p(stream.cuda_stream)
+
+    def factor(self):
+        ct, L = self.ct, self.L
+        h = ct.c_void_p()
+        rc = L.btd_factor(ct.byref(self.desc), self.A.data_ptr(), self.B.data_ptr(), self.C.data_ptr(),
+                          self.fptr, self.fb, self.sh, ct.byref(h))
+        if rc:
+            raise self.btd.BtdError(rc, "btd_factor")
+        self.plans.append(h)
+        return h
+
+    def solve(self, h):
+        rc = self.L.btd_solve(h, self.R, self.F.data_ptr(), self.X.data_ptr(), self.sptr, self.sb, self.sh)
+        if rc:
+            raise self.btd.BtdError(rc, "btd_solve")
+
     def step(self):
         ct, L = self.ct, self.L
         h = ct.c_void_p()
@@ -127,6 +148,63 @@ class Runner:
         for h in self.plans:
             self.L.btd_plan_destroy(h)
         self.plans = []
+
+
+def breakdown(torch, run, A, B, C, F, ms_step, reps=5):
+    """Outside the timed region: factor-only and solve-only times (the latter
+    with a resident plan), the same solve with one subsystem (the block
+    Thomas algorithm, P = 1) on the GPU, and the rates derived from them."""
+    from paper_1505_06864_amd import flops
+
+    def timed(fn, n):
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(n + 1)]
+        torch.cuda.synchronize()
+        evs[0].record(run.stream)
+        for k in range(n):
+            fn()
+            evs[k + 1].record(run.stream)
+        torch.cuda.synchronize()
+        return sum(evs[k].elapsed_time(evs[k + 1]) for k in range(n)) / n
+
+    factor_ms = timed(run.factor, reps)
+    run.release()
+    # the whole step captured once into a HIP graph and replayed: no launch
+    # gaps; every replay must give the eager step's X bit for bit
+    run.step()
+    torch.cuda.synchronize()
+    x_eager = run.X.clone()
+    run.release()
+    main_stream = run.stream
+    s = torch.cuda.Stream(device=A.device)
+    s.wait_stream(main_stream)
+    graph = torch.cuda.CUDAGraph()
+    run.use_stream(s)
+    with torch.cuda.graph(graph, stream=s):
+        run.step()
+    run.use_stream(main_stream)
+    run.X.zero_()
+    graph_ms = timed(graph.replay, reps)
+    graph_same = bool(torch.equal(run.X, x_eager))
+    del graph
+    run.release()
+    h = run.factor()
+    solve_ms = timed(lambda: run.solve(h), reps)
+    run.release()
+    N, M, _ = A.shape
+    R = F.shape[2]
+    ta = Runner(torch, A, B, C, F, 1, 0, 0)
+    ta.step()
+    ta.release()
+    ta_ms = timed(ta.step, 1)
+    ta.release()
+    ta_flops = sum(flops.totals(N, M, R, 1, 0))
+    return {"factor_ms": factor_ms, "solve_ms": solve_ms, "graph_ms_per_step": graph_ms,
+            "graph_replay_equals_eager": graph_same, "ta_one_subsystem_ms": ta_ms,
+            "speedup_vs_ta_on_gpu": ta_ms / ms_step,
+            "ta_equivalent_tflops": ta_flops / (ms_step * 1e-3) / 1e12,
+            "note": "factor and solve timed separately (resident plan for the solve); graph = the whole step "
+                    "(factor, solve, residual) captured once into a HIP graph and replayed; TA = the same library "
+                    "with P = 1 (one subsystem), timed once; speedup = TA time / DM time per solve"}
 
 
 def cpu_baseline(host_inputs, P, depth, rows, workload):
@@ -273,6 +351,8 @@ def main():
                      "avg_launch_ms": dom_avg_ms, "launches": dom_n,
                      "gflop_per_launch": dom_flops_per_launch / 1e9},
     }
+    if not args.no_breakdown:
+        out["breakdown"] = breakdown(torch, run, A, B, C, F, ms_step)
     if not args.no_cpu_baseline:
         rows = args.cpu_sample_rows or (768 if M >= 256 else (1024 if M >= 128 else N))
         out["cpu_baseline"] = cpu_baseline(host, P, depth, rows, args.workload)
