@@ -58,6 +58,9 @@ hipError_t launch_getrs(const KArgs& ka, hipStream_t s);
 hipError_t launch_chunk_solve(const KArgs& ka, hipStream_t s);
 hipError_t launch_init_status(unsigned long long* st, hipStream_t s);
 hipError_t launch_write_ints(int* dst, const int* host_vals, int count, hipStream_t s);
+// Partial sums per column of the residual kernels (their work array holds
+// 2 * residual_parts * R doubles).
+size_t residual_parts(int N, int M, int R);
 hipError_t launch_residual(int N, int M, int R, const double* A, const double* B, const double* C,
                            const double* X, const double* F, double* out, double* work, hipStream_t s);
 size_t getrf_lds_bytes(int M);

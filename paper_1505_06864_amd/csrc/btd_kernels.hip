@@ -2090,6 +2090,70 @@ __global__ __launch_bounds__(256) void k_residual_rows(int N, int M, int R, cons
     }
 }
 
+// The same for many right-hand sides: one workgroup per (block row, 64-row
+// tile of M, 64-column tile of R) forms the 64 x 64 tile of
+// A_i X_i + B_i X_{i-1} + C_i X_{i+1} on MFMA (the GEMM tile of the
+// factor products, three K sweeps), and writes the tile's per-column sums
+// of squares of r and F, reduced in a fixed order through LDS.
+constexpr int RES_TILE_MIN_R = 8;   // fewer columns: the row kernel (HBM-bound)
+
+__global__ __launch_bounds__(256) void k_residual_tiles(int N, int M, int R, const double* __restrict__ A,
+                                                       const double* __restrict__ B, const double* __restrict__ C,
+                                                       const double* __restrict__ X, const double* __restrict__ F,
+                                                       double* __restrict__ part) {
+    __shared__ double As[2 * ASZ];
+    __shared__ double Bs[2 * BSZ];
+    __shared__ double red[2][4][2][64];   // [r / F][wave][column tile][lane]
+    const int ntm = (M + TB - 1) / TB, ntn = (R + TB - 1) / TB;
+    int bid = blockIdx.x;
+    const int tn = bid % ntn;
+    bid /= ntn;
+    const int tm = bid % ntm, i = bid / ntm;
+    const int row0 = tm * TB, col0 = tn * TB;
+    const size_t MM = (size_t)M * M, MR = (size_t)M * R;
+    v4d acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) acc[a][c] = (v4d){0.0, 0.0, 0.0, 0.0};
+    tile_accumulate(A + i * MM, M, X + i * MR, R, M, row0, col0, M, R, acc, As, Bs);
+    if (i > 0) tile_accumulate(B + i * MM, M, X + (i - 1) * MR, R, M, row0, col0, M, R, acc, As, Bs);
+    if (i < N - 1) tile_accumulate(C + i * MM, M, X + (i + 1) * MR, R, M, row0, col0, M, R, acc, As, Bs);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const int col = col0 + wc + 16 * c + (lane & 15);
+        double sr = 0.0, sf = 0.0;
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = row0 + wr + 16 * a + (lane >> 4) + 4 * v;
+                if (row < M && col < R) {
+                    const double f = F[i * MR + (size_t)row * R + col];
+                    const double rv = f - acc[a][c][v];
+                    sr = fma(rv, rv, sr);
+                    sf = fma(f, f, sf);
+                }
+            }
+        red[0][w][c][lane] = sr;
+        red[1][w][c][lane] = sf;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 * TB) {
+        const int q = threadIdx.x & (TB - 1), k = threadIdx.x >> 6;   // column of the tile, r or F
+        const int wq = q >> 5, c = (q >> 4) & 1, l16 = q & 15;
+        double sum = 0.0;
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int g = 0; g < 4; ++g) sum += red[k][wq + 2 * h][c][l16 + 16 * g];
+        const int col = col0 + q;
+        if (col < R) part[(((size_t)col * N + i) * ntm + tm) * 2 + k] = sum;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_residual_final(int N, int R, const double* __restrict__ part,
                                                        double* __restrict__ out) {
     const int c = blockIdx.x;
@@ -2234,12 +2298,21 @@ hipError_t launch_write_ints(int* dst, const int* host_vals, int count, hipStrea
     return hipSuccess;
 }
 
+size_t residual_parts(int N, int M, int R) {
+    return (size_t)N * (R >= RES_TILE_MIN_R ? (size_t)cdiv(M, TB) : 1);
+}
+
 hipError_t launch_residual(int N, int M, int R, const double* A, const double* B, const double* C, const double* X,
                            const double* F, double* out, double* work, hipStream_t s) {
-    hipLaunchKernelGGL(k_residual_rows, dim3(N, R), dim3(256), 0, s, N, M, R, A, B, C, X, F, work);
+    if (R >= RES_TILE_MIN_R) {
+        const int ntm = cdiv(M, TB), ntn = cdiv(R, TB);
+        hipLaunchKernelGGL(k_residual_tiles, dim3(N * ntm * ntn), dim3(256), 0, s, N, M, R, A, B, C, X, F, work);
+    } else {
+        hipLaunchKernelGGL(k_residual_rows, dim3(N, R), dim3(256), 0, s, N, M, R, A, B, C, X, F, work);
+    }
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
-    hipLaunchKernelGGL(k_residual_final, dim3(R), dim3(256), 0, s, N, R, work, out);
+    hipLaunchKernelGGL(k_residual_final, dim3(R), dim3(256), 0, s, (int)residual_parts(N, M, R), R, work, out);
     return hipGetLastError();
 }
 

@@ -8,6 +8,8 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <algorithm>
+#include <cmath>
 #include <vector>
 
 #include "btd_internal.h"
@@ -413,9 +415,8 @@ int btd_solve_batch(int32_t count, const btd_plan_t* plans, const int32_t* nrhs,
 }
 
 size_t btd_residual_work_bytes(int32_t N, int32_t M, int32_t R) {
-    (void)M;
-    if (N < 1 || R < 1) return 0;
-    return sizeof(double) * 2 * (size_t)N * R;
+    if (N < 1 || M < 1 || R < 1) return 0;
+    return sizeof(double) * 2 * btd::residual_parts(N, M, R) * R;
 }
 
 int btd_residual(int32_t N, int32_t M, int32_t R, const double* A, const double* B, const double* C,
@@ -478,6 +479,38 @@ int btd_default_separators(int32_t N, int32_t P, int32_t* seps_out) {
     std::vector<int> sep;
     equal_split(N, P, sep);
     for (int k = 0; k < P - 1; ++k) seps_out[k] = sep[k + 1];
+    return BTD_OK;
+}
+
+int btd_balanced_separators(int32_t N, int32_t P, double alpha, double beta, int32_t* seps_out) {
+    if (N < 1 || P < 1 || (P > 1 && 2 * (int64_t)P - 1 > N) || (P > 1 && !seps_out)) return -1;
+    if (!(alpha >= 1.0 && alpha <= 64.0) || !(beta >= 1.0 && beta <= 64.0)) return -1;
+    if (P == 1) return BTD_OK;
+    // subsystem rows T = N - (P-1); the middle size x = T / (P - 2 + alpha + beta),
+    // the first alpha x and the last beta x (rounded), every subsystem >= 1 row
+    const int T = N - (P - 1);
+    const double x = T / (P - 2 + alpha + beta);
+    std::vector<int> n(P, 0);
+    int first = std::max(1, (int)std::lround(alpha * x)), last = std::max(1, (int)std::lround(beta * x));
+    if (P == 2) {
+        first = std::min(first, T - 1);
+        last = T - first;
+    } else {
+        while (T - first - last < P - 2) {   // room for one row per middle subsystem
+            if (first >= last) --first;
+            else --last;
+        }
+        const int rest = T - first - last, q = rest / (P - 2), r = rest % (P - 2);
+        for (int k = 1; k < P - 1; ++k) n[k] = q + (k - 1 < r ? 1 : 0);
+    }
+    n[0] = first;
+    n[P - 1] = last;
+    int pos = 0;
+    for (int k = 0; k < P - 1; ++k) {
+        pos += n[k];
+        seps_out[k] = pos;
+        pos += 1;
+    }
     return BTD_OK;
 }
 
