@@ -45,7 +45,7 @@ struct IntChunk {
     int v[CAP];
 };
 
-enum GemmMode { GM_FWD = 0, GM_BWD, GM_COUPLE, GM_COUPLE_RHS, GM_RECOVER };
+enum GemmMode { GM_FWD = 0, GM_BWD, GM_COUPLE, GM_COUPLE_RHS, GM_RECOVER, GM_RHS_FWD, GM_RHS_BWD };
 
 hipError_t launch_fwd_gemm(const KArgs& ka, hipStream_t s);
 hipError_t launch_bwd_gemm(const KArgs& ka, hipStream_t s);
@@ -56,6 +56,10 @@ hipError_t launch_getrf(const KArgs& ka, hipStream_t s);
 hipError_t launch_diag_inv(const KArgs& ka, hipStream_t s);
 hipError_t launch_getrs(const KArgs& ka, hipStream_t s);
 hipError_t launch_chunk_solve(const KArgs& ka, hipStream_t s);
+bool rhs_batched(int M, int R);
+hipError_t launch_rhs_fwd_gemm(const KArgs& ka, hipStream_t s);
+hipError_t launch_rhs_getrs(const KArgs& ka, hipStream_t s);
+hipError_t launch_rhs_bwd_gemm(const KArgs& ka, hipStream_t s);
 hipError_t launch_init_status(unsigned long long* st, hipStream_t s);
 hipError_t launch_write_ints(int* dst, const int* host_vals, int count, hipStream_t s);
 // Partial sums per column of the residual kernels (their work array holds

@@ -225,6 +225,32 @@ __device__ bool make_job(const KArgs& ka, int b, int part, Job& j) {
         j.A1 = L.B + q * MM; j.lda1 = M; j.B1 = ka.X + (q - 1) * MR; j.ldb1 = R; j.k1 = M;
         j.A2 = L.C + q * MM; j.lda2 = M; j.B2 = ka.X + (q + 1) * MR; j.ldb2 = R; j.k2 = M;
         return true;
+    } else if (MODE == GM_RHS_FWD) {
+        // right-hand-side sweep, chunk c0+b, step t: X_i = F_i - B_i X_{i-1}
+        // (X_{i-1} already solved), before the LU solve of row i
+        const int k = ka.c0 + b, t = ka.step, R = ka.R;
+        const int r = chunk_first(L, k), e = chunk_last(L, k);
+        if (t > e - r) return false;
+        const int i = r + t;
+        const size_t MR = (size_t)M * R;
+        j.n = R;
+        j.Out = ka.X + i * MR; j.ldo = R;
+        j.Cin = ka.F + i * MR; j.ldc = R;
+        if (t > 0) { j.A1 = L.B + i * MM; j.lda1 = M; j.B1 = ka.X + (i - 1) * MR; j.ldb1 = R; j.k1 = M; }
+        return true;
+    } else if (MODE == GM_RHS_BWD) {
+        // right-hand-side sweep, chunk c0+b, backward step s (row i = e-1-s):
+        // X_i -= E_i X_{i+1}
+        const int k = ka.c0 + b, s = ka.step, R = ka.R;
+        const int r = chunk_first(L, k), e = chunk_last(L, k);
+        if (s > e - r - 1) return false;
+        const int i = e - 1 - s;
+        const size_t MR = (size_t)M * R;
+        j.n = R;
+        j.Out = ka.X + i * MR; j.ldo = R;
+        j.Cin = ka.X + i * MR; j.ldc = R;
+        j.A1 = L.W + i * MM * 2; j.lda1 = M2; j.B1 = ka.X + (i + 1) * MR; j.ldb1 = R; j.k1 = M;
+        return true;
     } else if (MODE == GM_RECOVER) {
         // batch item = block row i; chunk rows: X_i -= Z_L h^{k-1} + Z_R h^k, separators: X_q = h
         const int i = b, R = ka.R, P = L.P;
@@ -1656,7 +1682,9 @@ __device__ __forceinline__ void tseq_run(v4d (&x)[NBLK][2][NT16], double* ring, 
     }
 }
 
-template <int NBLK, int NT16, int WPB>
+// RHS: the right-hand-side sweep's X_i (R columns, in place) instead of
+// W_i = [C_i | -B_i Y_{i-1}].
+template <int NBLK, int NT16, int WPB, bool RHS = false>
 __global__ __launch_bounds__(64 * WPB) void k_getrs_s(const KArgs ka, int nslab, int wpc) {
     __shared__ double ring[TS_RING * TS_BLOCK];
     const Level& L = ka.L;
@@ -1668,8 +1696,9 @@ __global__ __launch_bounds__(64 * WPB) void k_getrs_s(const KArgs ka, int nslab,
     const int i = r + t;
     constexpr int SW = 16 * NT16;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4, j = lane & 15;
-    const int e_hi = (i != L.N - 1) ? M : 0;          // E_i columns [0, e_hi)
-    const int y_hi = (k > 0) ? 2 * M : M;             // Y_i columns [M, y_hi)
+    // solved columns: E_i [0, e_hi) and Y_i [M, y_hi) of W_i, or [0, R) of X_i
+    const int e_hi = RHS ? ka.R : (i != L.N - 1) ? M : 0;
+    const int y_hi = RHS ? 0 : (k > 0) ? 2 * M : M;
     const int g0 = wgc * WPB * SW, g1 = min(g0 + WPB * SW, nslab * SW);
     if (!(g0 < e_hi || (g0 < y_hi && g1 > M))) return;   // nothing to solve in this workgroup
     const int slab = wgc * WPB + w;
@@ -1678,8 +1707,8 @@ __global__ __launch_bounds__(64 * WPB) void k_getrs_s(const KArgs ka, int nslab,
     const double* lu = L.LU + (size_t)i * M * M;
     const double* di = L.DI + (size_t)i * nblk * DI_STRIDE;
     const int* perm = L.perm + (size_t)i * M;
-    double* X = L.W + (size_t)i * M * 2 * M;
-    const int ld = 2 * M;
+    double* X = RHS ? ka.X + (size_t)i * M * ka.R : L.W + (size_t)i * M * 2 * M;
+    const int ld = RHS ? ka.R : 2 * M;
     // first blocks of the sequence in flight before the right-hand side is read
     constexpr int PC = 1024 / (64 * WPB);   // doubles of a staged block per thread
     double4 p0 = tseq_load<NBLK, PC>(0, lu, di, M, nblk, tid);
@@ -2223,10 +2252,10 @@ hipError_t launch_diag_inv(const KArgs& ka, hipStream_t s) {
 
 static int slab_width(int M) { return M <= 256 ? 32 : 16; }
 
-template <int NBLK, int NT16, int WPB = 4>
+template <int NBLK, int NT16, int WPB = 4, bool RHS = false>
 static void launch_getrs_s(const KArgs& ka, hipStream_t s) {
-    const int nslab = cdiv(2 * ka.L.M, 16 * NT16), wpc = cdiv(nslab, WPB);
-    hipLaunchKernelGGL((k_getrs_s<NBLK, NT16, WPB>), dim3(wpc * ka.nc), dim3(64 * WPB), 0, s, ka, nslab, wpc);
+    const int nslab = cdiv(RHS ? ka.R : 2 * ka.L.M, 16 * NT16), wpc = cdiv(nslab, WPB);
+    hipLaunchKernelGGL((k_getrs_s<NBLK, NT16, WPB, RHS>), dim3(wpc * ka.nc), dim3(64 * WPB), 0, s, ka, nslab, wpc);
 }
 
 // M <= 256: slabs of 32 columns (64 for M <= 64; 16 above M = 128, so that
@@ -2246,6 +2275,21 @@ hipError_t launch_getrs(const KArgs& ka, hipStream_t s) {
     const int sw = slab_width(M);
     dim3 grid(cdiv(2 * M, sw) * ka.nc);
     hipLaunchKernelGGL((k_getrs<16, 4>), grid, dim3(256), 0, s, ka);
+    return hipGetLastError();
+}
+
+// Right-hand-side sweep of many columns as batched steps over all chunks
+// (M <= 256): the product X_i = F_i - B_i X_{i-1}, the LU solve of X_i in
+// 16-column slabs, and after the forward steps X_i -= E_i X_{i+1}.
+bool rhs_batched(int M, int R) { return M <= 256 && R >= 16; }
+hipError_t launch_rhs_fwd_gemm(const KArgs& ka, hipStream_t s) { return launch_gemm<GM_RHS_FWD, 1>(ka, ka.nc, ka.L.M, ka.R, s); }
+hipError_t launch_rhs_bwd_gemm(const KArgs& ka, hipStream_t s) { return launch_gemm<GM_RHS_BWD, 1>(ka, ka.nc, ka.L.M, ka.R, s); }
+hipError_t launch_rhs_getrs(const KArgs& ka, hipStream_t s) {
+    const int nblk = cdiv(ka.L.M, DB);
+    if (nblk <= 1) launch_getrs_s<1, 1, 4, true>(ka, s);
+    else if (nblk <= 2) launch_getrs_s<2, 1, 4, true>(ka, s);
+    else if (nblk <= 4) launch_getrs_s<4, 1, 4, true>(ka, s);
+    else launch_getrs_s<8, 1, 4, true>(ka, s);
     return hipGetLastError();
 }
 

@@ -310,7 +310,20 @@ int enqueue_solve_level(const btd_plan_s* p, size_t l, int R, const double* F, d
     ka.status = p->status;
     ka.c0 = 0;
     ka.nc = LP.P;
-    BTD_TRY(timed(BTD_KC_RHS_SWEEP, s, btd::launch_chunk_solve, ka));
+    if (btd::rhs_batched(LP.M, R)) {
+        for (int t = 0; t < LP.nmax; ++t) {
+            ka.step = t;
+            BTD_TRY(timed(BTD_KC_RHS_SWEEP, s, btd::launch_rhs_fwd_gemm, ka));
+            BTD_TRY(timed(BTD_KC_RHS_SWEEP, s, btd::launch_rhs_getrs, ka));
+        }
+        for (int t = 0; t + 1 < LP.nmax; ++t) {
+            ka.step = t;
+            BTD_TRY(timed(BTD_KC_RHS_SWEEP, s, btd::launch_rhs_bwd_gemm, ka));
+        }
+        ka.step = 0;
+    } else {
+        BTD_TRY(timed(BTD_KC_RHS_SWEEP, s, btd::launch_chunk_solve, ka));
+    }
     if (LP.P > 1) {
         double* Fc = (double*)(sws + sws_off);
         const size_t next = align_up(sws_off + sizeof(double) * (size_t)(LP.P - 1) * LP.M * R);

@@ -119,6 +119,23 @@ def test_inplace_and_repeated_solves():
     plan.destroy()
 
 
+@pytest.mark.parametrize("N,M,R,P,depth", [(40, 256, 16, 5, 1), (33, 100, 40, 4, 0), (60, 32, 17, 20, 1)])
+def test_many_rhs_batched_sweep(N, M, R, P, depth):
+    """16 or more right-hand sides (the sweep as batched product and
+    triangular-solve steps over all subsystems), out of place, then in place
+    with fewer columns than the plan allows."""
+    torch = require_gpu()
+    A, B, C, F = inputs.diag_dominant(N, M, R, seed=500 + N + R)
+    check_case(torch, A, B, C, F, P, depth)
+    Ad, Bd, Cd = to_dev(torch, A, B, C)
+    plan = btd.factor(Ad, Bd, Cd, P=P, depth=depth, max_nrhs=R + 3)
+    Fd = to_dev(torch, F)[0]
+    plan.solve(Fd, Fd)
+    assert plan.info() == (0, -1, -1)
+    assert_parity(Fd.cpu().numpy(), oracle.dm_solve(A, B, C, F, P, depth=depth), TOL_X)
+    plan.destroy()
+
+
 def test_solve_batch_matches_single_solves():
     torch = require_gpu()
     plans, Fs, refs = [], [], []
