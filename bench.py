@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--depth", type=int, default=None)
     ap.add_argument("--coupling-rows", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--balanced", action="store_true",
+                    help="balanced partition of Sec. 4 (first / last subsystems 7/4 and 7/6 of the others)")
     ap.add_argument("--no-breakdown", action="store_true",
                     help="skip the factor-only / solve-only timings and the one-subsystem (TA) run")
     ap.add_argument("--cpu-sample-rows", type=int, default=None)
@@ -86,7 +88,7 @@ def make_inputs(torch, name, dev):
 class Runner:
     """Direct C-ABI calls with preallocated workspaces (no allocation per step)."""
 
-    def __init__(self, torch, A, B, C, F, P, depth, coupling_rows=0):
+    def __init__(self, torch, A, B, C, F, P, depth, coupling_rows=0, seps=None):
         import ctypes
         from paper_1505_06864_amd import btd
         self.ct, self.btd, self.torch = ctypes, btd, torch
@@ -94,8 +96,8 @@ class Runner:
         self.N, self.M, _ = A.shape
         self.R = F.shape[2]
         self.A, self.B, self.C, self.F = A, B, C, F
-        self.desc, self._keep = btd.make_desc(self.N, self.M, P, depth, self.R, None, coupling_rows)
-        fb, sb = btd.workspace_bytes(self.N, self.M, P, depth, self.R, None, coupling_rows)
+        self.desc, self._keep = btd.make_desc(self.N, self.M, P, depth, self.R, seps, coupling_rows)
+        fb, sb = btd.workspace_bytes(self.N, self.M, P, depth, self.R, seps, coupling_rows)
         self.fws, self.fptr = btd._aligned_buffer(fb, A.device)
         self.sws, self.sptr = btd._aligned_buffer(sb, A.device)
         self.fb, self.sb = fb, sb
@@ -278,14 +280,15 @@ def main():
     depth = args.depth if args.depth is not None else DEFAULT_DEPTH
     crow = args.coupling_rows if args.coupling_rows is not None else DEFAULT_COUPLING_ROWS
     (A, B, C, F), host = make_inputs(torch, args.workload, dev)
-    run = Runner(torch, A, B, C, F, P, depth, crow)
+    seps = btd.balanced_separators(N, P) if args.balanced else None
+    run = Runner(torch, A, B, C, F, P, depth, crow, seps)
 
     for _ in range(args.warmup):
         run.step()
     torch.cuda.synchronize()
     run.release()
 
-    per = flops.per_class(N, M, R, P, depth, R, None, crow)
+    per = flops.per_class(N, M, R, P, depth, R, seps, crow)
     # pick the kernel class with the largest device time (one untimed step per class)
     class_ms = {}
     for c in btd.KERNEL_CLASSES:
@@ -315,7 +318,7 @@ def main():
     resid = float(run.res.max().item())
     run.release()
 
-    fac, sol = flops.totals(N, M, R, P, depth, R, None, crow)
+    fac, sol = flops.totals(N, M, R, P, depth, R, seps, crow)
     ms_step = wall * 1e3 / args.steps
     # per launch = the class's algorithmic FLOPs over the launches actually made (chunk groups on
     # several streams split one step into several launches)
@@ -337,7 +340,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {gen} blocks, N={N}, M={M}, R={R}, FP64",
-                   "N": N, "M": M, "R": R, "P": P, "depth": depth, "coupling_rows": crow},
+                   "N": N, "M": M, "R": R, "P": P, "depth": depth, "coupling_rows": crow,
+                   "partition": "balanced (Sec. 4)" if args.balanced else "equal"},
         "tflops": tflops,
         "frac_fp64_peak": tflops / PEAK_FP64_TFLOPS,
         "gflop_per_solve": (fac + sol) / 1e9,
@@ -347,7 +351,7 @@ def main():
         "kernel_ms_per_step": {c: round(v, 3) for c, v in class_ms.items()},
         "roofline": {"kernel": dom, "bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
-                     "traffic": recorded_traffic(dom, args.workload, P, depth, crow),
+                     "traffic": None if args.balanced else recorded_traffic(dom, args.workload, P, depth, crow),
                      "avg_launch_ms": dom_avg_ms, "launches": dom_n,
                      "gflop_per_launch": dom_flops_per_launch / 1e9},
     }

@@ -188,6 +188,18 @@ int btd_plan_level_parts(btd_plan_t plan, int32_t level);
  * SuppMatrM rule described for btd_desc_t::depth; 1 = Thomas algorithm).
  * Both return -1 for invalid sizes. */
 int btd_default_separators(int32_t N, int32_t P, int32_t *seps_out);
+/* Host-only: the balanced partition of Sec. 4 (second case of the speedup
+ * analysis): the first and the last subsystem alpha and beta times as long
+ * as the middle ones, whose common size is (N - (P-1)) / (P - 2 + alpha +
+ * beta), so that on one processor per subsystem the end subsystems (which
+ * have one spike fewer) take as long as the middle ones; the paper's values
+ * for few right-hand sides are alpha = 7/4, beta = 7/6.  Sizes are rounded
+ * to whole rows (first alpha x and last beta x to the nearest row, the rest
+ * split evenly over the middle subsystems, the first of them one row longer
+ * when it does not divide), every subsystem at least one row.  Writes
+ * seps_out[P-1] (0-based separator rows, for btd_desc_t::seps); returns 0,
+ * or -1 for invalid sizes or alpha, beta outside [1, 64]. */
+int btd_balanced_separators(int32_t N, int32_t P, double alpha, double beta, int32_t *seps_out);
 int btd_default_coupling_parts(int32_t P, int32_t M, int32_t R);
 /* Subsystem count of the coupling system of a level with P subsystems for a
  * given coupling_rows (see btd_desc_t; 0 gives btd_default_coupling_parts).

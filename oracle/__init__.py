@@ -18,6 +18,9 @@ Functions and the passage each follows:
   gepp_solve     dense Gaussian elimination with partial pivoting.
   residual       ||F - A X||_2 / ||F||_2 per column.
   partition      equal-split separators (Sec. 2 and Sec. 5).
+  balanced_partition
+                 first and last subsystems alpha and beta times the middle
+                 ones (Sec. 4, second case of the speedup analysis).
   default_m      coupling-system subsystem count (Eq. SuppMatrM).
 """
 import ctypes
@@ -106,6 +109,41 @@ def partition(N, P):
     if s:
         raise ValueError(f"invalid partition N={N} P={P}")
     return [seps[i] for i in range(P - 1)]
+
+
+def balanced_partition(N, P, alpha=7.0 / 4.0, beta=7.0 / 6.0):
+    """Separator rows (0-based, length P-1) with subsystem sizes
+    n_1 = alpha x, n_P = beta x and x for the others, x = (N - (P-1)) /
+    (P - 2 + alpha + beta) (Sec. 4, second case).  Whole rows: the two end
+    sizes rounded to the nearest row (at least one), shortened alternately
+    (the longer first) while the middle subsystems would get less than one
+    row each; the remaining rows split evenly over the middle subsystems,
+    the leading ones one row longer."""
+    if N < 1 or P < 1 or (P > 1 and 2 * P - 1 > N):
+        raise ValueError(f"invalid partition N={N} P={P}")
+    if P == 1:
+        return []
+    rows = N - (P - 1)
+    x = rows / (P - 2 + alpha + beta)
+    first = max(1, int(np.floor(alpha * x + 0.5)))
+    last = max(1, int(np.floor(beta * x + 0.5)))
+    if P == 2:
+        first = min(first, rows - 1)
+        sizes = [first, rows - first]
+    else:
+        while rows - first - last < P - 2:
+            if first >= last:
+                first -= 1
+            else:
+                last -= 1
+        q, r = divmod(rows - first - last, P - 2)
+        sizes = [first] + [q + (1 if k < r else 0) for k in range(P - 2)] + [last]
+    seps, pos = [], 0
+    for n in sizes[:-1]:
+        pos += n
+        seps.append(pos)
+        pos += 1
+    return seps
 
 
 def default_m(P, M, R):

@@ -23,8 +23,8 @@ BTD_MAX_M = 512
 # Every symbol include/btd.h declares.
 EXPORTS = ("btd_workspace_bytes", "btd_factor", "btd_solve", "btd_solve_batch", "btd_residual_work_bytes",
            "btd_residual", "btd_get_info", "btd_plan_separators", "btd_plan_level_parts",
-           "btd_default_separators", "btd_default_coupling_parts", "btd_coupling_parts", "btd_profile_enable",
-           "btd_profile_read",
+           "btd_default_separators", "btd_balanced_separators", "btd_default_coupling_parts",
+           "btd_coupling_parts", "btd_profile_enable", "btd_profile_read",
            "btd_plan_destroy", "btd_status_string")
 
 # Kernel classes of btd_profile_enable (BTD_KC_*).
@@ -61,6 +61,7 @@ def lib():
         L.btd_plan_separators.argtypes = [vp, ctypes.POINTER(i32)]
         L.btd_plan_level_parts.argtypes = [vp, i32]
         L.btd_default_separators.argtypes = [i32, i32, ctypes.POINTER(i32)]
+        L.btd_balanced_separators.argtypes = [i32, i32, ctypes.c_double, ctypes.c_double, ctypes.POINTER(i32)]
         L.btd_default_coupling_parts.argtypes = [i32, i32, i32]
         L.btd_coupling_parts.argtypes = [i32, i32, i32, i32]
         L.btd_profile_enable.argtypes = [i32]
@@ -134,6 +135,16 @@ def default_separators(N, P):
     rc = lib().btd_default_separators(N, P, out)
     if rc != BTD_OK:
         raise BtdError(rc, "btd_default_separators")
+    return [out[k] for k in range(P - 1)]
+
+
+def balanced_separators(N, P, alpha=7.0 / 4.0, beta=7.0 / 6.0):
+    """Separator rows of the balanced partition (Sec. 4: first and last
+    subsystems alpha and beta times the middle ones), host only."""
+    out = (ctypes.c_int32 * max(P - 1, 1))()
+    rc = lib().btd_balanced_separators(N, P, ctypes.c_double(alpha), ctypes.c_double(beta), out)
+    if rc != BTD_OK:
+        raise BtdError(rc, "btd_balanced_separators")
     return [out[k] for k in range(P - 1)]
 
 

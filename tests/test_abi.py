@@ -80,6 +80,18 @@ def test_partition_matches_oracle():
         assert btd.default_separators(N, P) == oracle.partition(N, P)
 
 
+def test_balanced_partition_matches_oracle():
+    for N in range(1, 70):
+        for P in range(1, (N + 1) // 2 + 1):
+            for a, b in ((7 / 4, 7 / 6), (1.0, 1.0), (2.5, 1.25), (9.0, 1.0)):
+                assert btd.balanced_separators(N, P, a, b) == oracle.balanced_partition(N, P, a, b), (N, P, a, b)
+    for N, P in ((3071, 16), (4096, 256), (2048, 512)):
+        assert btd.balanced_separators(N, P) == oracle.balanced_partition(N, P)
+    for bad in ((6, 4, 1.75, 1.2), (10, 2, 0.5, 1.0), (10, 2, 1.0, 100.0), (0, 1, 1.0, 1.0)):
+        with pytest.raises(btd.BtdError):
+            btd.balanced_separators(*bad)
+
+
 def test_coupling_parts_match_oracle():
     for P in range(1, 700):
         for M, R in ((16, 1), (128, 4), (256, 64)):

@@ -237,6 +237,33 @@ def test_partition_rule():
         oracle.partition(6, 4)
 
 
+def test_balanced_partition_rule():
+    """Sec. 4, second case: end subsystems alpha and beta times the middle
+    ones, N_k = (N - (P-1)) / (P - 2 + alpha + beta), in whole rows."""
+    for N in range(3, 120, 7):
+        for P in range(2, (N + 1) // 2 + 1):
+            for a, b in ((7 / 4, 7 / 6), (1.0, 1.0), (3.0, 1.5)):
+                seps = oracle.balanced_partition(N, P, a, b)
+                bounds = [-1] + seps + [N]
+                n = [bounds[k + 1] - bounds[k] - 1 for k in range(P)]
+                assert sum(n) == N - (P - 1) and min(n) >= 1
+                x = (N - P + 1) / (P - 2 + a + b)
+                if P > 2:
+                    assert max(n[1:-1]) - min(n[1:-1]) <= 1
+                    if x * min(a, b) >= 1 and N - P + 1 - round(a * x) - round(b * x) >= P - 2:
+                        assert abs(n[0] - a * x) <= 0.5 + 1e-9 and abs(n[-1] - b * x) <= 0.5 + 1e-9
+                if a == b == 1.0:
+                    assert max(n) - min(n) <= 1 + (P == 2)
+    # the paper's validation size (N = 3071 block rows), P = 16: middle size
+    # (3071 - 15) / (14 + 7/4 + 7/6) = 180.7
+    seps = oracle.balanced_partition(3071, 16)
+    bounds = [-1] + seps + [3071]
+    n = [bounds[k + 1] - bounds[k] - 1 for k in range(16)]
+    assert n[0] == 316 and n[-1] == 211 and set(n[1:-1]) <= {180, 181}
+    with pytest.raises(ValueError):
+        oracle.balanced_partition(6, 4)
+
+
 def test_default_m_rule():
     # Eq. SuppMatrM for P >= 21, boundary m = P/3 below, at least 2
     assert oracle.default_m(3, 16, 1) == 1
