@@ -1082,20 +1082,32 @@ __global__ __launch_bounds__(LW_NT) void k_getrf_pw(const KArgs ka) {
                             }
                 }
             }
-            // factor rows of panel q left of the slabs (multipliers from the working
-            // copy, the panel from LDS, the next panel's U12), the pivot order, and
-            // the multipliers of the rows left back to the working copy
-            const int W1 = min(M, j0q + NB + nb);
+            // factor rows of panel q: the multipliers left of the panel from the
+            // working copy (eight loads in flight per lane), the panel from LDS,
+            // the next panel's U12; the pivot order; the multipliers of the rows
+            // left back to the working copy
+            const int hs = (w - 1) * 64 + lane;
+            const int n0 = NB * j0q;
+            for (int base = hs; base < n0; base += 8 * LW_HW * 64) {
+                double val[8];
+#pragma unroll
+                for (int u8 = 0; u8 < 8; ++u8) {
+                    const int x = base + u8 * LW_HW * 64, rr = x / j0q, c = x - rr * j0q;
+                    val[u8] = x < n0 ? a[(size_t)pvq[rr] * M + c] : 0.0;
+                }
+#pragma unroll
+                for (int u8 = 0; u8 < 8; ++u8) {
+                    const int x = base + u8 * LW_HW * 64, rr = x / j0q, c = x - rr * j0q;
+                    if (x < n0) out[(size_t)(j0q + rr) * M + c] = val[u8];
+                }
+            }
+            const int W1 = min(M - j0q, NB + nb);   // panel q and the next panel's columns
             const int n1 = NB * W1, n2 = hq * NB;
-            for (int x = (w - 1) * 64 + lane; x < n1 + n2; x += LW_HW * 64) {
+            for (int x = hs; x < n1 + n2; x += LW_HW * 64) {
                 if (x < n1) {
                     const int rr = x / W1, c = x - rr * W1;
                     const int prow = pvq[rr];
-                    double val;
-                    if (c < j0q) val = a[(size_t)prow * M + c];
-                    else if (c < j0q + NB) val = lbq[prow * P + c - j0q];
-                    else val = UN[rr * P + c - j0q - NB];
-                    out[(size_t)(j0q + rr) * M + c] = val;
+                    out[(size_t)(j0q + rr) * M + j0q + c] = c < NB ? lbq[prow * P + c] : UN[rr * P + c - NB];
                     if (c == 0) perm[j0q + rr] = prow;
                 } else {
                     const int y = x - n1, ri = y / NB, c = y - ri * NB;
@@ -1162,16 +1174,27 @@ __global__ __launch_bounds__(LW_NT) void k_getrf_pw(const KArgs ka) {
         }
         __syncthreads();
     }
-    // ---------------- factor rows of the last panel, the failure report
+    // ---------------- factor rows of the last panel (eight loads in flight per
+    // thread), the failure report
     {
         const int j0 = p * NB, nb = M - j0, cur = p & 1;
         const int* pv = PIV + cur * NB;
         const double* lb = LB + (size_t)cur * 256 * P;
-        for (int x = tid; x < nb * M; x += LW_NT) {
-            const int rr = x / M, c = x - rr * M;
-            const int prow = pv[rr];
-            out[(size_t)(j0 + rr) * M + c] = c < j0 ? a[(size_t)prow * M + c] : lb[prow * P + c - j0];
-            if (c == 0) perm[j0 + rr] = prow;
+        for (int base = tid; base < nb * M; base += 8 * LW_NT) {
+            double val[8];
+#pragma unroll
+            for (int u8 = 0; u8 < 8; ++u8) {
+                const int x = base + u8 * LW_NT, rr = x / M, c = x - rr * M;
+                val[u8] = x < nb * M ? (c < j0 ? a[(size_t)pv[rr] * M + c] : lb[pv[rr] * P + c - j0]) : 0.0;
+            }
+#pragma unroll
+            for (int u8 = 0; u8 < 8; ++u8) {
+                const int x = base + u8 * LW_NT, rr = x / M, c = x - rr * M;
+                if (x < nb * M) {
+                    out[(size_t)(j0 + rr) * M + c] = val[u8];
+                    if (c == 0) perm[j0 + rr] = pv[rr];
+                }
+            }
         }
     }
     if (w == 0 && lane0 == 0 && fail_code != 0) report_status(ka.status, L.level, i, fail_col, fail_code);
