@@ -73,7 +73,7 @@ def test_small_workload(P, depth):
 @pytest.mark.parametrize("N,M,R,P,depth", [
     (1, 5, 1, 1, 0), (2, 3, 2, 1, 0), (3, 1, 1, 2, 0), (5, 1, 3, 3, 0), (13, 17, 1, 5, 0),
     (40, 33, 5, 6, 1), (21, 65, 33, 4, 0), (30, 100, 2, 7, 1), (9, 129, 65, 3, 0), (12, 64, 64, 4, 0),
-    (25, 31, 7, 12, 1),
+    (25, 31, 7, 12, 1), (9, 257, 3, 3, 1), (6, 300, 20, 2, 0), (10, 256, 1, 4, 0),
 ])
 def test_ragged_shapes(N, M, R, P, depth):
     torch = require_gpu()
@@ -167,18 +167,20 @@ def test_coupling_rows_split(coupling_rows, depth):
     check_case(torch, A, B, C, F, 64, depth, coupling_rows=coupling_rows)
 
 
-def test_pivoting_needed():
-    """Diagonal blocks whose leading entries are zero: LU without row
-    interchanges would break down."""
+@pytest.mark.parametrize("N,M,P", [(12, 8, 3), (9, 40, 3), (8, 100, 2), (6, 256, 2), (5, 300, 2)])
+def test_pivoting_needed(N, M, P):
+    """Diagonal blocks with rows permuted (and a zero leading entry): LU
+    without row interchanges would break down, and the pivot rows come in
+    scattered order across the panels of the LU."""
     torch = require_gpu()
-    rng = np.random.default_rng(31)
-    N, M, R = 12, 8, 2
-    A, B, C, F = inputs.diag_dominant(N, M, R, seed=31)
+    rng = np.random.default_rng(31 + M)
+    R = 2
+    A, B, C, F = inputs.diag_dominant(N, M, R, seed=31 + M)
     perm = rng.permutation(M)
     A = A[:, perm, :].copy()          # row-permuted diagonal blocks: zero-free but far from the diagonal
     A[:, 0, 0] = 0.0
     F = inputs.block_matvec(A, B, C, rng.standard_normal((N, M, R)))
-    check_case(torch, A, B, C, F, 3, 0)
+    check_case(torch, A, B, C, F, P, 0)
 
 
 def test_singular_block_reported():
