@@ -349,6 +349,10 @@ def main():
         "p99_ms": float(np.percentile(lat, 99)),
         "residual_max": resid,
         "kernel_ms_per_step": {c: round(v, 3) for c, v in class_ms.items()},
+        # algorithmic FLOPs of a class per second of its own launches (summed
+        # over the side streams, so concurrent launches each count in full)
+        "class_tflops": {c: round(per[c][0] / (v * 1e-3) / 1e12, 2) for c, v in class_ms.items()
+                         if v > 0 and per[c][0] > 0},
         "roofline": {"kernel": dom, "bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
                      "traffic": None if args.balanced else recorded_traffic(dom, args.workload, P, depth, crow),
