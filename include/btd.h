@@ -140,9 +140,13 @@ int btd_solve(btd_plan_t plan, int32_t nrhs, const double *F, double *X, void *s
 /*
  * Solve several factored systems in one call: for s < count,
  * X[s] = A_s^{-1} F[s] with nrhs[s] columns.  plans, nrhs, F, X are HOST
- * arrays of length count (F[s], X[s] device pointers).  The solves run one
- * after another on `stream` sharing solve_ws, which must be at least the
- * largest solve size of the plans.
+ * arrays of length count (F[s], X[s] device pointers).  solve_ws must be at
+ * least the largest solve size of the plans; with room for k such solves
+ * (each rounded up to 256 bytes), up to k of them (at most 4) run side by side on the
+ * library's side streams, each in its own slice of solve_ws, forked from and
+ * joined back to `stream`; otherwise they run one after another on `stream`.
+ * Results do not depend on which: every solve is the same computation.
+ * Entries must not share an X array.
  * Returns 0; -1 count < 0 or a NULL array; -(1000 + s) for the first bad
  * entry s (NULL plan or pointer, nrhs out of range); -6 NULL, misaligned or
  * too small solve_ws; BTD_ERR_LAUNCH.

@@ -244,13 +244,14 @@ def factor(A, B, C, P=1, depth=0, max_nrhs=1, seps=None, stream=None, coupling_r
     return Plan(A, B, C, P=P, depth=depth, max_nrhs=max_nrhs, seps=seps, stream=stream, coupling_rows=coupling_rows)
 
 
-def solve_batch(plans, Fs, Xs=None, stream=None):
-    """btd_solve_batch over several plans; returns the list of solutions."""
+def solve_batch(plans, Fs, Xs=None, stream=None, lanes=1):
+    """btd_solve_batch over several plans; returns the list of solutions.
+    lanes > 1 gives the call room for that many solves side by side."""
     torch = _torch()
     n = len(plans)
     if Xs is None:
         Xs = [torch.empty_like(F) for F in Fs]
-    nbytes = max(p.solve_bytes for p in plans) if n else 256
+    nbytes = max(lanes, 1) * ((max(p.solve_bytes for p in plans) + 255) // 256 * 256) if n else 256
     buf, ptr = _aligned_buffer(nbytes, Fs[0].device if n else "cuda")
     hp = (ctypes.c_void_p * max(n, 1))(*[p.handle.value for p in plans])
     nr = (ctypes.c_int32 * max(n, 1))(*[F.shape[2] for F in Fs])

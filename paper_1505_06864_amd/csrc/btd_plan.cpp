@@ -9,7 +9,6 @@
 #include <cstring>
 #include <new>
 #include <algorithm>
-#include <cmath>
 #include <vector>
 
 #include "btd_internal.h"
@@ -420,9 +419,34 @@ int btd_solve_batch(int32_t count, const btd_plan_t* plans, const int32_t* nrhs,
         }
         if (!solve_ws || ((uintptr_t)solve_ws % kAlign) != 0 || solve_bytes < need) return -6;
     }
+    if (count == 0) return BTD_OK;
+    hipStream_t s0 = (hipStream_t)stream;
+    // with room for k solves in solve_ws, up to k of them run side by side on
+    // the library's side streams, each in its own slice of the workspace
+    size_t need = 0;
+    for (int s = 0; s < count; ++s) need = std::max(need, solve_bytes_for(plans[s]->levels, nrhs[s]));
+    const size_t slice = align_up(need);
+    int lanes = (int)std::min<size_t>({solve_bytes / slice, (size_t)kMaxGroups, (size_t)count});
+    StreamPool* pool = lanes > 1 ? stream_pool() : nullptr;
+    if (!pool) lanes = 1;
+    if (lanes == 1) {
+        for (int s = 0; s < count; ++s) {
+            int rc = enqueue_solve_level(plans[s], 0, nrhs[s], F[s], X[s], (char*)solve_ws, 0, s0);
+            if (rc != BTD_OK) return rc;
+        }
+        return BTD_OK;
+    }
+    BTD_TRY(hipEventRecord(pool->fork, s0));
+    for (int g = 0; g < lanes; ++g) BTD_TRY(hipStreamWaitEvent(pool->s[g], pool->fork, 0));
     for (int s = 0; s < count; ++s) {
-        int rc = enqueue_solve_level(plans[s], 0, nrhs[s], F[s], X[s], (char*)solve_ws, 0, (hipStream_t)stream);
+        const int g = s % lanes;
+        int rc = enqueue_solve_level(plans[s], 0, nrhs[s], F[s], X[s], (char*)solve_ws + (size_t)g * slice, 0,
+                                     pool->s[g]);
         if (rc != BTD_OK) return rc;
+    }
+    for (int g = 0; g < lanes; ++g) {
+        BTD_TRY(hipEventRecord(pool->join[g], pool->s[g]));
+        BTD_TRY(hipStreamWaitEvent(s0, pool->join[g], 0));
     }
     return BTD_OK;
 }

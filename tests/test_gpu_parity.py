@@ -148,6 +148,13 @@ def test_solve_batch_matches_single_solves():
     Xs = btd.solve_batch(plans, Fs)
     for X, Xo in zip(Xs, refs):
         assert_parity(X.cpu().numpy(), Xo, TOL_X)
+    # with room for three solves side by side: the same numbers, bit for bit
+    for lanes in (2, 3):
+        Xc = btd.solve_batch(plans, Fs, lanes=lanes)
+        for X, Y in zip(Xs, Xc):
+            assert torch.equal(X, Y)
+    for p in plans:
+        p.destroy()
 
 
 def test_deterministic():
