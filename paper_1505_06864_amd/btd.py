@@ -227,6 +227,16 @@ class Plan:
             parts.append(p)
             lvl += 1
 
+    def release_after_work(self):
+        """Destroy the plan without waiting for the device: only for a plan
+        whose enqueued work is known to have finished (its workspace returns
+        to the stream it was allocated on)."""
+        if getattr(self, "_h", None):
+            lib().btd_plan_destroy(self._h)
+            self._h = None
+            self._ws = None
+            self._last_solve_ws = None
+
     def destroy(self):
         if getattr(self, "_h", None):
             _torch().cuda.synchronize(self.device)
