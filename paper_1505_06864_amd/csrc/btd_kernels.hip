@@ -2142,12 +2142,12 @@ __global__ __launch_bounds__(256) void k_residual_rows(int N, int M, int R, cons
     }
 }
 
-// The same for many right-hand sides: one workgroup per (block row, 64-row
+// The same for two or more right-hand sides: one workgroup per (block row, 64-row
 // tile of M, 64-column tile of R) forms the 64 x 64 tile of
 // A_i X_i + B_i X_{i-1} + C_i X_{i+1} on MFMA (the GEMM tile of the
 // factor products, three K sweeps), and writes the tile's per-column sums
 // of squares of r and F, reduced in a fixed order through LDS.
-constexpr int RES_TILE_MIN_R = 8;   // fewer columns: the row kernel (HBM-bound)
+constexpr int RES_TILE_MIN_R = 2;   // one column: the row kernel (HBM-bound)
 
 __global__ __launch_bounds__(256) void k_residual_tiles(int N, int M, int R, const double* __restrict__ A,
                                                        const double* __restrict__ B, const double* __restrict__ C,

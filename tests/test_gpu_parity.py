@@ -49,8 +49,8 @@ def check_case(torch, A, B, C, F, P, depth=0, seps=None, inplace=False, coupling
                                    (1, 16, 8), (9, 16, 8), (5, 256, 64), (7, 33, 70), (3, 130, 9)])
 def test_residual_kernel_matches_oracle(N, M, R):
     """The device residual of a perturbed solution (residual well above
-    rounding) against the oracle's residual of the same X (R >= 8 takes the
-    MFMA tile kernel, fewer columns the row kernel).  The perturbation keeps
+    rounding) against the oracle's residual of the same X (R >= 2 takes the
+    MFMA tile kernel, one column the row kernel).  The perturbation keeps
     ||r|| near 1e-3 ||F||: the rounding of A X (about 3 M u |A||X| per
     element, in either accumulation order) is then near 1e-12 of ||r||, well
     inside the 1e-10 bar."""
