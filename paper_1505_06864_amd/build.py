@@ -9,8 +9,13 @@ LIB = os.path.join(HERE, "libbtd.so")
 SOURCES = ["btd_kernels.hip", "btd_plan.cpp"]
 ARCH = "gfx950"
 
-# Packed-FP32 instruction selection is switched off for device code.
-DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# Packed-FP32 instruction selection is switched off for device code.  MFMA
+# accumulators are kept in ordinary VGPRs (gfx950 reads and writes them there
+# directly): with the AGPR form the compiler copies the accumulators of the
+# GEMM K loops out of and back into AGPRs on every K step, which drains the
+# matrix pipeline each time.
+DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                "-mllvm", "-amdgpu-mfma-vgpr-form"]
 
 
 def hipcc() -> str:
