@@ -241,8 +241,9 @@ def recorded_traffic(kclass, workload, P, depth, coupling_rows):
     """HBM bytes per launch of a kernel class from the committed rocprofv3
     counter summary (FETCH_SIZE + WRITE_SIZE, each scaled against a plain copy
     kernel), or None when there is none for this workload and plan or the
-    kernel source has changed since the counters were taken."""
-    import hashlib
+    kernel source or its compile flags have changed since the counters were
+    taken."""
+    from paper_1505_06864_amd.build import kernel_build_sha256
     path = os.path.join(ROOT, "profiles", f"{kclass}_{workload}_traffic.txt")
     if not os.path.exists(path):
         return None
@@ -252,9 +253,7 @@ def recorded_traffic(kclass, workload, P, depth, coupling_rows):
             continue
         k, v = line.split(":", 1)
         kv[k.strip()] = v.strip()
-    src = os.path.join(ROOT, "paper_1505_06864_amd", "csrc", "btd_kernels.hip")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if (kv.get("kernel_source_sha256") != sha or kv.get("kernel_class") != kclass
+    if (kv.get("kernel_build_sha256") != kernel_build_sha256() or kv.get("kernel_class") != kclass
             or kv.get("P") != str(P) or kv.get("depth") != str(depth)
             or kv.get("coupling_rows") != str(coupling_rows)):
         return None

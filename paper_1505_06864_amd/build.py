@@ -18,6 +18,15 @@ DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
                 "-mllvm", "-amdgpu-mfma-vgpr-form"]
 
 
+def kernel_build_sha256() -> str:
+    """sha256 over the kernel source and the device compile flags: identifies
+    the machine code that a recorded measurement (HBM counters) belongs to."""
+    import hashlib
+    h = hashlib.sha256(open(os.path.join(CSRC, "btd_kernels.hip"), "rb").read())
+    h.update(("\n" + " ".join(DEVICE_FLAGS)).encode())
+    return h.hexdigest()
+
+
 def hipcc() -> str:
     for cand in (os.environ.get("HIPCC"), shutil.which("hipcc"), "/opt/rocm/bin/hipcc"):
         if cand and os.path.exists(cand):
