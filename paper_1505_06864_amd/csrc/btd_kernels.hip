@@ -283,6 +283,7 @@ __device__ bool make_job(const KArgs& ka, int b, int part, Job& j) {
 constexpr int TB = 64, KB = 16, AP = 4, BP = 4;
 constexpr int ASZ = KB * (TB + AP), BSZ = KB * (TB + BP);
 
+template <bool FULL>
 __device__ __forceinline__ void load_tiles(const double* __restrict__ A, int lda, const double* __restrict__ Bm,
                                            int ldb, int row0, int col0, int k0, int m, int n, int K, double ra[4],
                                            double rb[4]) {
@@ -290,7 +291,7 @@ __device__ __forceinline__ void load_tiles(const double* __restrict__ A, int lda
     {
         const int rr = tid >> 2, kq = (tid & 3) * 4;
         const int gr = row0 + rr, gk = k0 + kq;
-        if (gr < m && gk + 3 < K && (lda & 3) == 0) {
+        if (FULL || (gr < m && gk + 3 < K && (lda & 3) == 0)) {
             const double4 x = *(const double4*)(A + (size_t)gr * lda + gk);
             ra[0] = x.x; ra[1] = x.y; ra[2] = x.z; ra[3] = x.w;
         } else {
@@ -301,7 +302,7 @@ __device__ __forceinline__ void load_tiles(const double* __restrict__ A, int lda
     {
         const int kk = tid >> 4, cq = (tid & 15) * 4;
         const int gk = k0 + kk, gc = col0 + cq;
-        if (gk < K && gc + 3 < n && (ldb & 3) == 0) {
+        if (FULL || (gk < K && gc + 3 < n && (ldb & 3) == 0)) {
             const double4 x = *(const double4*)(Bm + (size_t)gk * ldb + gc);
             rb[0] = x.x; rb[1] = x.y; rb[2] = x.z; rb[3] = x.w;
         } else {
@@ -324,42 +325,84 @@ __device__ __forceinline__ void store_tiles(double* As, double* Bs, const double
     }
 }
 
-__device__ void tile_accumulate(const double* __restrict__ A, int lda, const double* __restrict__ Bm, int ldb,
-                                int K, int row0, int col0, int m, int n, v4d acc[2][2], double* As, double* Bs) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
-    double ra[4], rb[4];
-    if (K <= 0) return;
-    load_tiles(A, lda, Bm, ldb, row0, col0, 0, m, n, K, ra, rb);
-    __syncthreads();   // the buffers may still be read by a previous accumulation
-    store_tiles(As, Bs, ra, rb);
-    __syncthreads();
-    int buf = 0;
-    for (int k0 = 0; k0 < K; k0 += KB) {
-        const bool more = k0 + KB < K;
-        if (more) load_tiles(A, lda, Bm, ldb, row0, col0, k0 + KB, m, n, K, ra, rb);
-        const double* as = As + buf * ASZ;
-        const double* bs = Bs + buf * BSZ;
+__device__ __forceinline__ void tile_mma(const double* as, const double* bs, int lane, int wr, int wc,
+                                         v4d acc[2][2]) {
 #pragma unroll
-        for (int kk = 0; kk < KB / 4; ++kk) {
-            const int krow = kk * 4 + (lane >> 4);
-            double a0 = as[krow * (TB + AP) + wr + (lane & 15)];
-            double a1 = as[krow * (TB + AP) + wr + 16 + (lane & 15)];
-            double b0 = bs[krow * (TB + BP) + wc + (lane & 15)];
-            double b1 = bs[krow * (TB + BP) + wc + 16 + (lane & 15)];
-            acc[0][0] = mfma4(a0, b0, acc[0][0]);
-            acc[0][1] = mfma4(a0, b1, acc[0][1]);
-            acc[1][0] = mfma4(a1, b0, acc[1][0]);
-            acc[1][1] = mfma4(a1, b1, acc[1][1]);
-        }
-        if (more) store_tiles(As + (buf ^ 1) * ASZ, Bs + (buf ^ 1) * BSZ, ra, rb);
-        __syncthreads();
-        buf ^= 1;
+    for (int kk = 0; kk < KB / 4; ++kk) {
+        const int krow = kk * 4 + (lane >> 4);
+        double a0 = as[krow * (TB + AP) + wr + (lane & 15)];
+        double a1 = as[krow * (TB + AP) + wr + 16 + (lane & 15)];
+        double b0 = bs[krow * (TB + BP) + wc + (lane & 15)];
+        double b1 = bs[krow * (TB + BP) + wc + 16 + (lane & 15)];
+        acc[0][0] = mfma4(a0, b0, acc[0][0]);
+        acc[0][1] = mfma4(a0, b1, acc[0][1]);
+        acc[1][0] = mfma4(a1, b0, acc[1][0]);
+        acc[1][1] = mfma4(a1, b1, acc[1][1]);
     }
 }
 
+// The global loads run two K steps ahead of the products: while step s is
+// multiplied from one LDS buffer, step s+1 (loaded during step s-1) goes
+// from registers into the other buffer and step s+2 is in flight in a
+// second register set, so a load has two steps of products to arrive.
+// FULL: the tile lies inside the matrix, K is a multiple of two K steps and
+// the rows are 32-byte aligned; every load is then unconditional (the last
+// two steps load the final K step again, unused), which keeps the loop free
+// of branches, so the loads of step s+2 stay in flight while step s+1 is
+// stored.
+template <bool FULL>
+__device__ void tile_accumulate_k(const double* __restrict__ A, int lda, const double* __restrict__ Bm, int ldb,
+                                  int K, int row0, int col0, int m, int n, v4d acc[2][2], double* As, double* Bs) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+    double ra0[4], rb0[4], ra1[4], rb1[4];
+    const int nk = (K + KB - 1) / KB;
+    load_tiles<FULL>(A, lda, Bm, ldb, row0, col0, 0, m, n, K, ra0, rb0);
+    if (FULL || nk > 1) load_tiles<FULL>(A, lda, Bm, ldb, row0, col0, KB, m, n, K, ra1, rb1);
+    __syncthreads();   // the buffers may still be read by a previous accumulation
+    store_tiles(As, Bs, ra0, rb0);
+    __syncthreads();
+    if constexpr (FULL) {
+        for (int s = 0; s < nk; s += 2) {
+            load_tiles<true>(A, lda, Bm, ldb, row0, col0, min(s + 2, nk - 1) * KB, m, n, K, ra0, rb0);
+            tile_mma(As, Bs, lane, wr, wc, acc);
+            store_tiles(As + ASZ, Bs + BSZ, ra1, rb1);
+            __syncthreads();
+            load_tiles<true>(A, lda, Bm, ldb, row0, col0, min(s + 3, nk - 1) * KB, m, n, K, ra1, rb1);
+            tile_mma(As + ASZ, Bs + BSZ, lane, wr, wc, acc);
+            store_tiles(As, Bs, ra0, rb0);
+            __syncthreads();
+        }
+    } else {
+        for (int s = 0; s < nk; s += 2) {
+            // step s from buffer 0; step s+1 in ra1/rb1; ra0/rb0 free
+            if (s + 2 < nk) load_tiles<false>(A, lda, Bm, ldb, row0, col0, (s + 2) * KB, m, n, K, ra0, rb0);
+            tile_mma(As, Bs, lane, wr, wc, acc);
+            if (s + 1 < nk) store_tiles(As + ASZ, Bs + BSZ, ra1, rb1);
+            __syncthreads();
+            if (s + 1 >= nk) break;
+            // step s+1 from buffer 1; step s+2 in ra0/rb0; ra1/rb1 free
+            if (s + 3 < nk) load_tiles<false>(A, lda, Bm, ldb, row0, col0, (s + 3) * KB, m, n, K, ra1, rb1);
+            tile_mma(As + ASZ, Bs + BSZ, lane, wr, wc, acc);
+            if (s + 2 < nk) store_tiles(As, Bs, ra0, rb0);
+            __syncthreads();
+        }
+    }
+}
+
+__device__ void tile_accumulate(const double* __restrict__ A, int lda, const double* __restrict__ Bm, int ldb,
+                                int K, int row0, int col0, int m, int n, v4d acc[2][2], double* As, double* Bs) {
+    if (K <= 0) return;
+    const bool full = row0 + TB <= m && col0 + TB <= n && K % (2 * KB) == 0 && (lda & 3) == 0 &&
+                      (ldb & 3) == 0 && ((uintptr_t)A & 31) == 0 && ((uintptr_t)Bm & 31) == 0;
+    if (full) tile_accumulate_k<true>(A, lda, Bm, ldb, K, row0, col0, m, n, acc, As, Bs);
+    else tile_accumulate_k<false>(A, lda, Bm, ldb, K, row0, col0, m, n, acc, As, Bs);
+}
+
+// At most 128 VGPRs (four waves per SIMD, as many as the LDS admits) except
+// for the coupling right-hand sides, whose job set-up needs more.
 template <int MODE, int NPARTS>
-__global__ __launch_bounds__(256) void k_gemm(const KArgs ka, int tiles_m, int tiles_n) {
+__global__ __launch_bounds__(256, MODE == GM_COUPLE_RHS ? 3 : 4) void k_gemm(const KArgs ka, int tiles_m, int tiles_n) {
     __shared__ double As[2 * ASZ];
     __shared__ double Bs[2 * BSZ];
     const int per_item = tiles_m * tiles_n * NPARTS;
