@@ -1079,50 +1079,81 @@ __global__ __launch_bounds__(LW_NT) void k_getrf_pw(const KArgs ka) {
             const int* lsq = LIST + qc * 256;
             const double* lbq = LB + (size_t)qc * 256 * P;
             double* nxd = NX + (size_t)nxt * 256 * P;   // columns of panel p+1
+            // Every load below is unconditional, from a clamped address (row 0
+            // or column 0 for the rows and columns outside the update), so that
+            // the loop has no divergent branches: the loads of one 64-row batch
+            // stay in flight while the previous batch is multiplied.  Entries
+            // of rows or columns outside the update are never stored, and a
+            // tile row or column does not reach any other in the product.
             for (int s = w - 1; s < nsl; s += LW_HW) {
                 const int col = cs0 + s * NB + cc;
                 const bool cok = col < M;
+                const int cs = cok ? col : 0;
                 double bo[4];
 #pragma unroll
-                for (int kk = 0; kk < 4; ++kk) bo[kk] = cok ? a[(size_t)pvq[4 * kk + g] * M + col] : 0.0;
+                for (int kk = 0; kk < 4; ++kk) bo[kk] = a[(size_t)pvq[4 * kk + g] * M + cs];
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) bo[kk] = cok ? bo[kk] : 0.0;
                 v4d u = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
                 for (int kk = 0; kk < 4; ++kk) u = mfma4(TB[cc * P + 4 * kk + g], bo[kk], u);
 #pragma unroll
                 for (int vv = 0; vv < 4; ++vv)
                     if (cok) out[(size_t)(j0q + g + 4 * vv) * M + col] = u[vv];
-                // A22 -= L21 U12 over the rows left, four 16-row tiles per batch
-                for (int tb = 0; tb < hq; tb += 64) {
-                    v4d cv[4];
-                    int rw[4][4];
+                // A22 -= L21 U12 over the rows left, four 16-row tiles per
+                // batch; hq <= 240, so a batch index stays below 256
+                const int nbt = (hq + 63) / 64;
+                auto load_batch = [&](int tb, v4d (&c)[4], int (&rw)[4][4]) {
 #pragma unroll
                     for (int x = 0; x < 4; ++x)
 #pragma unroll
                         for (int vv = 0; vv < 4; ++vv) {
                             const int idx = tb + 16 * x + g + 4 * vv;
-                            rw[x][vv] = idx < hq ? lsq[idx] : -1;
+                            const int lv = lsq[idx];
+                            rw[x][vv] = idx < hq ? lv : -1;
                         }
 #pragma unroll
                     for (int x = 0; x < 4; ++x)
 #pragma unroll
                         for (int vv = 0; vv < 4; ++vv)
-                            cv[x][vv] = (rw[x][vv] >= 0 && cok) ? a[(uint32_t)(rw[x][vv] * M + col)] : 0.0;
+                            c[x][vv] = a[(uint32_t)(max(rw[x][vv], 0) * M + cs)];
+                };
+                auto mul_store = [&](int tb, v4d (&c)[4], const int (&rw)[4][4]) {
+                    double ao[4][4];
 #pragma unroll
                     for (int x = 0; x < 4; ++x) {
                         const int ai = tb + 16 * x + cc;
-                        const int ar = ai < hq ? lsq[ai] : -1;
+                        const int lv = lsq[ai];
+                        const int ar = ai < hq ? lv : -1;
 #pragma unroll
-                        for (int kk = 0; kk < 4; ++kk)
-                            cv[x] = mfma4(ar >= 0 ? -lbq[ar * P + 4 * kk + g] : 0.0, u[kk], cv[x]);
+                        for (int kk = 0; kk < 4; ++kk) {
+                            const double l = lbq[max(ar, 0) * P + 4 * kk + g];
+                            ao[x][kk] = ar >= 0 ? -l : 0.0;
+                        }
                     }
+#pragma unroll
+                    for (int x = 0; x < 4; ++x)
+#pragma unroll
+                        for (int kk = 0; kk < 4; ++kk) c[x] = mfma4(ao[x][kk], u[kk], c[x]);
 #pragma unroll
                     for (int x = 0; x < 4; ++x)
 #pragma unroll
                         for (int vv = 0; vv < 4; ++vv)
                             if (rw[x][vv] >= 0 && cok) {
-                                if (s == 0) nxd[rw[x][vv] * P + cc] = cv[x][vv];
-                                else a[(uint32_t)(rw[x][vv] * M + col)] = cv[x][vv];
+                                if (s == 0) nxd[rw[x][vv] * P + cc] = c[x][vv];
+                                else a[(uint32_t)(rw[x][vv] * M + col)] = c[x][vv];
                             }
+                };
+                v4d c0[4], c1[4];
+                int r0[4][4], r1[4][4];
+                load_batch(0, c0, r0);
+                for (int bt = 0; bt < nbt; bt += 2) {
+                    // the batch after this one (the last one again at the end, unused)
+                    load_batch(min(bt + 1, nbt - 1) * 64, c1, r1);
+                    mul_store(bt * 64, c0, r0);
+                    if (bt + 1 >= nbt) break;
+                    load_batch(min(bt + 2, nbt - 1) * 64, c0, r0);
+                    mul_store((bt + 1) * 64, c1, r1);
                 }
             }
             // factor rows of panel q: the multipliers left of the panel from the
