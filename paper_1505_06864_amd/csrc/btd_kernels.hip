@@ -1214,9 +1214,14 @@ __global__ __launch_bounds__(LW_NT) void k_getrf_pw(const KArgs ka) {
             wave_lds_sync();
             const double* nxn = NX + (size_t)nxt * 256 * P;
             v4d acc = {0.0, 0.0, 0.0, 0.0};
+            double bn[4];
 #pragma unroll
-            for (int kk = 0; kk < 4; ++kk)
-                acc = mfma4(TB[cc * P + 4 * kk + g], cc < nb2 ? nxn[pv[4 * kk + g] * P + cc] : 0.0, acc);
+            for (int kk = 0; kk < 4; ++kk) {
+                const double x = nxn[pv[4 * kk + g] * P + cc];   // cc < 16 < P: inside the row
+                bn[kk] = cc < nb2 ? x : 0.0;
+            }
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) acc = mfma4(TB[cc * P + 4 * kk + g], bn[kk], acc);
 #pragma unroll
             for (int vv = 0; vv < 4; ++vv) UN[(g + 4 * vv) * P + cc] = acc[vv];
         }
@@ -1226,21 +1231,30 @@ __global__ __launch_bounds__(LW_NT) void k_getrf_pw(const KArgs ka) {
             const double* lb = LB + (size_t)cur * 256 * P;
             const int* ls = LIST + cur * 256;
             double* nxn = NX + (size_t)nxt * 256 * P;
+            // reads from clamped LDS addresses (w2 <= 240, so every index
+            // stays below 256), no divergent branch; rows outside are not stored
             for (int tb = w * 16; tb < w2; tb += 8 * 16) {
                 int rw[4];
 #pragma unroll
                 for (int vv = 0; vv < 4; ++vv) {
                     const int idx = tb + g + 4 * vv;
-                    rw[vv] = idx < w2 ? ls[idx] : -1;
+                    const int lv = ls[idx];
+                    rw[vv] = idx < w2 ? lv : -1;
                 }
                 v4d cv;
 #pragma unroll
-                for (int vv = 0; vv < 4; ++vv) cv[vv] = rw[vv] >= 0 ? nxn[rw[vv] * P + cc] : 0.0;
+                for (int vv = 0; vv < 4; ++vv) cv[vv] = nxn[max(rw[vv], 0) * P + cc];
                 const int ai = tb + cc;
-                const int ar = ai < w2 ? ls[ai] : -1;
+                const int lv = ls[ai];
+                const int ar = ai < w2 ? lv : -1;
+                double ao[4];
 #pragma unroll
-                for (int kk = 0; kk < 4; ++kk)
-                    cv = mfma4(ar >= 0 ? -lb[ar * P + 4 * kk + g] : 0.0, UN[(4 * kk + g) * P + cc], cv);
+                for (int kk = 0; kk < 4; ++kk) {
+                    const double l = lb[max(ar, 0) * P + 4 * kk + g];
+                    ao[kk] = ar >= 0 ? -l : 0.0;
+                }
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) cv = mfma4(ao[kk], UN[(4 * kk + g) * P + cc], cv);
 #pragma unroll
                 for (int vv = 0; vv < 4; ++vv)
                     if (rw[vv] >= 0) nxn[rw[vv] * P + cc] = cv[vv];
