@@ -1695,52 +1695,61 @@ __host__ __device__ constexpr int tseq_bp(int e) {
                   : tseq_b<NBLK>(e);
 }
 
-// This thread's piece of sequence element e (PC = 4 or 2 consecutive
-// doubles of one block row; negated for pairs).
+// This thread's piece of sequence element e: PC = 4 or 2 consecutive doubles
+// of one block row, loaded as they are.  Every load is made, from a clamped
+// address where the piece reaches past the matrix; the bits of `valid` say
+// which values are inside.  The sign change of the pairs and the zeros
+// outside are applied when the piece is staged, two elements later: no
+// divergent branch and no use of the loaded values follows the loads, so
+// the loads of later elements stay in flight while earlier pieces are
+// staged.
 template <int NBLK, int PC>
 __device__ __forceinline__ double4 tseq_load(int e, const double* __restrict__ lu, const double* __restrict__ di,
-                                             int M, int nblk, int tid) {
+                                             int M, int nblk, int tid, int& valid) {
     const int kind = tseq_kind<NBLK>(e), b = tseq_b<NBLK>(e), bp = tseq_bp<NBLK>(e);
     constexpr int PR = DB / PC;   // pieces per block row
     const int r = tid / PR, c4 = (tid % PR) * PC;
-    double4 v = {0.0, 0.0, 0.0, 0.0};
+    double q[4] = {0.0, 0.0, 0.0, 0.0};
+    valid = 0;
     if (kind == 0 || kind == 2) {
         const int row = bp * DB + r, col = b * DB + c4;
-        if (row < M) {
-            if (PC == 4 && col + 3 < M && (M & 3) == 0) {
-                v = *(const double4*)(lu + (uint32_t)(row * M + col));
-            } else if (PC == 2 && col + 1 < M && (M & 1) == 0) {
-                const double2 h = *(const double2*)(lu + (uint32_t)(row * M + col));
-                v.x = h.x; v.y = h.y;
-            } else {
-                v.x = col < M ? lu[(uint32_t)(row * M + col)] : 0.0;
-                v.y = col + 1 < M ? lu[(uint32_t)(row * M + col + 1)] : 0.0;
-                if (PC == 4) {
-                    v.z = col + 2 < M ? lu[(uint32_t)(row * M + col + 2)] : 0.0;
-                    v.w = col + 3 < M ? lu[(uint32_t)(row * M + col + 3)] : 0.0;
-                }
-            }
-            v.x = -v.x; v.y = -v.y; v.z = -v.z; v.w = -v.w;
+        const int rs = row < M ? row : 0;
+#pragma unroll
+        for (int u = 0; u < PC; ++u) {
+            q[u] = lu[(uint32_t)(rs * M + min(col + u, M - 1))];
+            valid |= (row < M && col + u < M) ? 1 << u : 0;
         }
-    } else if (b < nblk) {
-        const double* src = di + (size_t)b * DI_STRIDE + (kind == 3 ? DB * DB : 0) + r * DB + c4;
-        if (PC == 4) v = *(const double4*)src;
-        else { const double2 h = *(const double2*)src; v.x = h.x; v.y = h.y; }
+    } else {
+        const int bs = b < nblk ? b : 0;
+        const double* src = di + (size_t)bs * DI_STRIDE + (kind == 3 ? DB * DB : 0) + r * DB + c4;
+        if (PC == 4) {
+            const double4 v = *(const double4*)src;
+            q[0] = v.x; q[1] = v.y; q[2] = v.z; q[3] = v.w;
+        } else {
+            const double2 h = *(const double2*)src;
+            q[0] = h.x; q[1] = h.y;
+        }
+        valid = b < nblk ? 15 : 0;
     }
-    return v;
+    return make_double4(q[0], q[1], q[2], q[3]);
 }
 
-// Store a piece in operand order: block row r is row tile tr = (r >> 2) & 1,
+// Store a piece of sequence element e in operand order (negated for pairs,
+// zeros outside the matrix): block row r is row tile tr = (r >> 2) & 1,
 // tile row i16 = (r >> 3) | ((r & 3) << 2); column c = 8 g + kk.
-template <int PC>
-__device__ __forceinline__ void tseq_stage(double* slot, int tid, double4 v) {
+template <int NBLK, int PC>
+__device__ __forceinline__ void tseq_stage(int e, double* slot, int tid, double4 v, int valid) {
     constexpr int PR = DB / PC;
+    const int kind = tseq_kind<NBLK>(e);
+    const double sg = (kind == 0 || kind == 2) ? -1.0 : 1.0;
+    const double x0 = (valid & 1) ? sg * v.x : 0.0, x1 = (valid & 2) ? sg * v.y : 0.0;
+    const double x2 = (valid & 4) ? sg * v.z : 0.0, x3 = (valid & 8) ? sg * v.w : 0.0;
     const int r = tid / PR, c4 = (tid % PR) * PC;
     const int tr = (r >> 2) & 1, i16 = (r >> 3) | ((r & 3) << 2);
     const int g = c4 >> 3, kk = c4 & 7;
     double* d = slot + (tr * 64 + g * 16 + i16) * TS_LANE + kk;
-    *(double2*)d = make_double2(v.x, v.y);
-    if (PC == 4) *(double2*)(d + 2) = make_double2(v.z, v.w);
+    *(double2*)d = make_double2(x0, x1);
+    if (PC == 4) *(double2*)(d + 2) = make_double2(x2, x3);
 }
 
 template <int NBLK, int NT16, int E>
@@ -1777,19 +1786,21 @@ __device__ __forceinline__ void tseq_apply(v4d (&x)[NBLK][2][NT16], const double
 }
 
 // Sequence element E: stage E+1 (loaded two elements ago), start loading
-// E+3, apply E, barrier.  p0/p1 hold the pieces of E+1 and E+2 on entry.
+// E+3, apply E, barrier.  p0/p1 (validity m0/m1) hold the pieces of E+1 and
+// E+2 on entry.
 template <int NBLK, int NT16, int PC, int E>
 __device__ __forceinline__ void tseq_run(v4d (&x)[NBLK][2][NT16], double* ring, const double* __restrict__ lu,
                                          const double* __restrict__ di, int M, int nblk, int tid, int lane,
-                                         double4& p0, double4& p1) {
+                                         double4& p0, int m0, double4& p1, int m1) {
     constexpr int NS = trsm_nseq<NBLK>();
     if constexpr (E < NS) {
-        if constexpr (E + 1 < NS) tseq_stage<PC>(ring + ((E + 1) % TS_RING) * TS_BLOCK, tid, p0);
+        if constexpr (E + 1 < NS) tseq_stage<NBLK, PC>(E + 1, ring + ((E + 1) % TS_RING) * TS_BLOCK, tid, p0, m0);
         double4 p2 = {0.0, 0.0, 0.0, 0.0};
-        if constexpr (E + 3 < NS) p2 = tseq_load<NBLK, PC>(E + 3, lu, di, M, nblk, tid);
+        int m2 = 0;
+        if constexpr (E + 3 < NS) p2 = tseq_load<NBLK, PC>(E + 3, lu, di, M, nblk, tid, m2);
         tseq_apply<NBLK, NT16, E>(x, ring + (E % TS_RING) * TS_BLOCK, lane);
         __syncthreads();
-        tseq_run<NBLK, NT16, PC, E + 1>(x, ring, lu, di, M, nblk, tid, lane, p1, p2);
+        tseq_run<NBLK, NT16, PC, E + 1>(x, ring, lu, di, M, nblk, tid, lane, p1, m1, p2, m2);
     }
 }
 
@@ -1822,9 +1833,13 @@ __global__ __launch_bounds__(64 * WPB) void k_getrs_s(const KArgs ka, int nslab,
     const int ld = RHS ? ka.R : 2 * M;
     // first blocks of the sequence in flight before the right-hand side is read
     constexpr int PC = 1024 / (64 * WPB);   // doubles of a staged block per thread
-    double4 p0 = tseq_load<NBLK, PC>(0, lu, di, M, nblk, tid);
-    double4 p1 = tseq_load<NBLK, PC>(1, lu, di, M, nblk, tid);
-    double4 p2 = tseq_load<NBLK, PC>(2, lu, di, M, nblk, tid);
+    int m0, m1, m2;
+    double4 p0 = tseq_load<NBLK, PC>(0, lu, di, M, nblk, tid, m0);
+    double4 p1 = tseq_load<NBLK, PC>(1, lu, di, M, nblk, tid, m1);
+    double4 p2 = tseq_load<NBLK, PC>(2, lu, di, M, nblk, tid, m2);
+    // the right-hand side from the pivot rows (perm holds valid rows), every
+    // load unconditional from a clamped row and column; zeros outside after
+    // all loads are out
     v4d x[NBLK][2][NT16];
 #pragma unroll
     for (int b = 0; b < NBLK; ++b)
@@ -1832,22 +1847,33 @@ __global__ __launch_bounds__(64 * WPB) void k_getrs_s(const KArgs ka, int nslab,
         for (int tr = 0; tr < 2; ++tr) {
             int prw[4];
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int row = b * DB + 8 * g + 4 * tr + v;
-                prw[v] = row < M ? perm[row] : -1;
+            for (int v = 0; v < 4; ++v) prw[v] = perm[min(b * DB + 8 * g + 4 * tr + v, M - 1)];
+#pragma unroll
+            for (int nt = 0; nt < NT16; ++nt) {
+                const int col = c0 + 16 * nt + j;
+                const bool cv = col < e_hi || (col >= M && col < y_hi);
+                const int cs = cv ? col : 0;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) x[b][tr][nt][v] = X[(uint32_t)(prw[v] * ld + cs)];
             }
+        }
+#pragma unroll
+    for (int b = 0; b < NBLK; ++b)
+#pragma unroll
+        for (int tr = 0; tr < 2; ++tr)
 #pragma unroll
             for (int nt = 0; nt < NT16; ++nt) {
                 const int col = c0 + 16 * nt + j;
                 const bool cv = col < e_hi || (col >= M && col < y_hi);
 #pragma unroll
-                for (int v = 0; v < 4; ++v)
-                    x[b][tr][nt][v] = (cv && prw[v] >= 0) ? X[(uint32_t)(prw[v] * ld + col)] : 0.0;
+                for (int v = 0; v < 4; ++v) {
+                    const int row = b * DB + 8 * g + 4 * tr + v;
+                    x[b][tr][nt][v] = (cv && row < M) ? x[b][tr][nt][v] : 0.0;
+                }
             }
-        }
-    tseq_stage<PC>(ring, tid, p0);
+    tseq_stage<NBLK, PC>(0, ring, tid, p0, m0);
     __syncthreads();
-    tseq_run<NBLK, NT16, PC, 0>(x, ring, lu, di, M, nblk, tid, lane, p1, p2);
+    tseq_run<NBLK, NT16, PC, 0>(x, ring, lu, di, M, nblk, tid, lane, p1, m1, p2, m2);
 #pragma unroll
     for (int b = 0; b < NBLK; ++b)
 #pragma unroll
