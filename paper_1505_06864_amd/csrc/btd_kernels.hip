@@ -170,7 +170,9 @@ __device__ bool make_job(const KArgs& ka, int b, int part, Job& j) {
             j.Out = L.Dw + k * MM; j.ldo = M;
             j.Cin = L.A + i * MM; j.ldc = M;
             if (t > 0) { j.A1 = L.B + i * MM; j.lda1 = M; j.B1 = L.W + (i - 1) * MM * 2; j.ldb1 = M2; j.k1 = M; }
-            if (i != L.N - 1) { j.CopyIn = L.C + i * MM; j.ldci = M; j.CopyOut = L.W + i * MM * 2; j.ldco = M2; }
+            // C_i -> W_i[:, :M] only for the workgroup slab solve (M > 256); the
+            // wave-slab solve reads C_i itself
+            if (i != L.N - 1 && M > 256) { j.CopyIn = L.C + i * MM; j.ldci = M; j.CopyOut = L.W + i * MM * 2; j.ldco = M2; }
             return true;
         }
         if (k == 0) return false;
@@ -1839,7 +1841,10 @@ __global__ __launch_bounds__(64 * WPB) void k_getrs_s(const KArgs ka, int nslab,
     double4 p2 = tseq_load<NBLK, PC>(2, lu, di, M, nblk, tid, m2);
     // the right-hand side from the pivot rows (perm holds valid rows), every
     // load unconditional from a clamped row and column; zeros outside after
-    // all loads are out
+    // all loads are out.  The E half of W_i starts as C_i and is read from C
+    // (the forward product does not copy it for this kernel); the solution
+    // goes to W_i.
+    const double* Ci = RHS ? X : L.C + (size_t)i * M * M;
     v4d x[NBLK][2][NT16];
 #pragma unroll
     for (int b = 0; b < NBLK; ++b)
@@ -1852,9 +1857,12 @@ __global__ __launch_bounds__(64 * WPB) void k_getrs_s(const KArgs ka, int nslab,
             for (int nt = 0; nt < NT16; ++nt) {
                 const int col = c0 + 16 * nt + j;
                 const bool cv = col < e_hi || (col >= M && col < y_hi);
+                const bool fromC = !RHS && cv && col < M;
+                const double* src = fromC ? Ci : X;
+                const int lds = fromC ? M : ld;
                 const int cs = cv ? col : 0;
 #pragma unroll
-                for (int v = 0; v < 4; ++v) x[b][tr][nt][v] = X[(uint32_t)(prw[v] * ld + cs)];
+                for (int v = 0; v < 4; ++v) x[b][tr][nt][v] = src[(uint32_t)(prw[v] * lds + cs)];
             }
         }
 #pragma unroll
