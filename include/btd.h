@@ -38,8 +38,12 @@
  *     BTD_ERR_LAUNCH means a HIP launch failed (work enqueued before it may
  *     still run).  Numerical failures are found on the device and read back
  *     with btd_get_info after the stream has been synchronised.
- *   - Calls on one plan are not thread-safe; distinct plans may be used on
- *     distinct streams concurrently.
+ *   - Calls on one plan are not thread-safe.  Distinct plans may be used
+ *     from distinct host threads on distinct streams: every call orders its
+ *     own work with events of the calling thread, so no call waits on
+ *     another call's stream.  The library's side streams (at most four per
+ *     device, created once) are shared by all threads, so concurrent calls
+ *     are correct but their side-stream launches interleave in issue order.
  */
 #ifndef BTD_H
 #define BTD_H
@@ -156,6 +160,75 @@ int btd_solve_batch(int32_t count, const btd_plan_t *plans, const int32_t *nrhs,
                     void *stream);
 
 /*
+ * The two halves of btd_solve, for a caller that solves the coupling system
+ * itself (for instance with the coupling blocks of btd_plan_level_arrays,
+ * or sharded over several devices):
+ *
+ * btd_solve_local: the per-subsystem part (Sec. 2, Eq. e231 for the
+ * right-hand side, and the vector part of Eq. e2311).  Writes z, the
+ * solution of every subsystem with its right-hand side F alone, into the
+ * subsystem rows of X (separator rows of X are left untouched), and the
+ * coupling right-hand side f_j = F_q - B_q z_{q-1} - C_q z_{q+1} of every
+ * separator q = q_j into Fhat, a DEVICE array [P-1][M][nrhs] (level 0
+ * sizes).  With P = 1 it is the whole solve and Fhat is not used (may be
+ * NULL).  X may equal F.
+ * btd_solve_finish: given the coupling solution h ([P-1][M][nrhs], DEVICE;
+ * may be the Fhat array solved in place) and X from btd_solve_local,
+ * writes X_q = h_j at the separators and recovers the subsystem rows,
+ * X_i = z_i - Z_L[i] h_{k-1} - Z_R[i] h_k (Eq. endSolution).
+ * Neither needs a workspace.  Both return 0; -1 NULL plan; -2 nrhs out of
+ * range; -3/-4 NULL F/X (finish: -3 NULL H when P > 1, -4 NULL X); -5 NULL
+ * Fhat when P > 1; BTD_ERR_LAUNCH.  btd_solve_local also records the
+ * right-hand-side check of btd_get_solve_info.
+ */
+int btd_solve_local(btd_plan_t plan, int32_t nrhs, const double *F, double *X, double *Fhat, void *stream);
+int btd_solve_finish(btd_plan_t plan, int32_t nrhs, const double *H, double *X, void *stream);
+
+/*
+ * Status of the right-hand side of the last btd_solve, btd_solve_local or
+ * btd_solve_batch entry of `plan`; call after synchronising its stream.
+ * Every solve first checks F: *status = BTD_ERR_NONFINITE when F holds a
+ * NaN or an infinity, with *block_row = the first such block row i and
+ * *col = its right-hand-side column (the smallest (row, column) pair);
+ * BTD_OK and -1, -1 otherwise.  Any output pointer may be NULL.  Performs a
+ * blocking device-to-host copy.  Returns 0, -1 for a NULL plan, or
+ * BTD_ERR_LAUNCH.
+ */
+int btd_get_solve_info(btd_plan_t plan, int32_t *status, int32_t *block_row, int32_t *col);
+
+/*
+ * Read-only device views of one recursion level of a factored plan (level 0
+ * = the caller's system; level l >= 1 = the coupling system of level l-1,
+ * whose blocks are Hd, Hb, Hc of that level).  For inspection and for
+ * callers that build on the intermediates of Sec. 2:
+ *   N, M, P   sizes of the level's system and its subsystem count;
+ *   A, B, C   the level's blocks ([N][M][M]);
+ *   W         [N][M][2M]: columns 0..M-1 of row i hold E_i = D_i^{-1} C_i
+ *             (the forward auxiliary of Sec. 3; at the last row of a
+ *             subsystem with a right spike it is the spike's seed D^{-1} C,
+ *             and it is not defined at the last row of the last subsystem);
+ *             columns M..2M-1 hold the forward sweep Y of the left spike in
+ *             subsystems k >= 1 (Eq. e231);
+ *   Z         [N][M][2M]: [Z_L | Z_R], the spikes of Eq. e231 at subsystem
+ *             rows (Z_L defined for k >= 1, Z_R for k <= P-2); NULL when P = 1;
+ *   Hd, Hb, Hc  [P-1][M][M]: diagonal, sub- and super-diagonal blocks of the
+ *             coupling system (Eq. e2311); NULL when P = 1;
+ *   sep       [P+1] device ints: -1, the P-1 separator rows, N.
+ * The arrays live in the plan's factor workspace and are valid after the
+ * factor's stream has been synchronised and until the next btd_factor into
+ * the same workspace.  Returns 0, or -1 for a NULL plan or output, or a
+ * level past the last.
+ */
+typedef struct {
+    int32_t N, M, P;
+    const double *A, *B, *C;
+    const double *W, *Z;
+    const double *Hd, *Hb, *Hc;
+    const int32_t *sep;
+} btd_level_arrays_t;
+int btd_plan_level_arrays(btd_plan_t plan, int32_t level, btd_level_arrays_t *out);
+
+/*
  * Relative residual per column (the check of a solve; not a step of the
  * paper): out[c] = ||F[:,c] - (A X)[:,c]||_2 / ||F[:,c]||_2, or the
  * unscaled norm when F[:,c] = 0.  A, B, C, X, F are device pointers, out is
@@ -216,8 +289,8 @@ int btd_coupling_parts(int32_t P, int32_t M, int32_t R, int32_t coupling_rows);
  * pair of HIP events recorded on the launch's stream.  btd_profile_read
  * waits for the recorded events, returns the summed elapsed milliseconds and
  * the number of launches since the last read, and releases the events.
- * Classes: see BTD_KC_*.  btd_profile_enable(-1) disables.  Not
- * thread-safe.  Returns 0, or -1 for an unknown class.
+ * Classes: see BTD_KC_*.  btd_profile_enable(-1) disables.  The record is
+ * process-wide (guarded by a lock).  Returns 0, or -1 for an unknown class.
  */
 #define BTD_KC_FWD_GEMM 0     /* D_i = A_i - B_i E_{i-1} and the left-spike product       */
 #define BTD_KC_GETRF 1        /* LU with partial pivoting of D_i                          */

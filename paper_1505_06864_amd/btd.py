@@ -21,7 +21,8 @@ BTD_PREC_F64 = 0
 BTD_MAX_M = 512
 
 # Every symbol include/btd.h declares.
-EXPORTS = ("btd_workspace_bytes", "btd_factor", "btd_solve", "btd_solve_batch", "btd_residual_work_bytes",
+EXPORTS = ("btd_workspace_bytes", "btd_factor", "btd_solve", "btd_solve_batch", "btd_solve_local",
+           "btd_solve_finish", "btd_get_solve_info", "btd_plan_level_arrays", "btd_residual_work_bytes",
            "btd_residual", "btd_get_info", "btd_plan_separators", "btd_plan_level_parts",
            "btd_default_separators", "btd_balanced_separators", "btd_default_coupling_parts",
            "btd_coupling_parts", "btd_profile_enable", "btd_profile_read",
@@ -36,6 +37,11 @@ class Desc(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int32), ("M", ctypes.c_int32), ("P", ctypes.c_int32),
                 ("depth", ctypes.c_int32), ("prec", ctypes.c_int32), ("max_nrhs", ctypes.c_int32),
                 ("seps", ctypes.POINTER(ctypes.c_int32)), ("coupling_rows", ctypes.c_int32)]
+
+
+class LevelArrays(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int32), ("M", ctypes.c_int32), ("P", ctypes.c_int32)] + \
+               [(n, ctypes.c_void_p) for n in ("A", "B", "C", "W", "Z", "Hd", "Hb", "Hc", "sep")]
 
 
 _lib = None
@@ -54,6 +60,10 @@ def lib():
         L.btd_solve.argtypes = [vp, i32, vp, vp, vp, sz, vp]
         L.btd_solve_batch.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(i32), ctypes.POINTER(vp),
                                       ctypes.POINTER(vp), vp, sz, vp]
+        L.btd_solve_local.argtypes = [vp, i32, vp, vp, vp, vp]
+        L.btd_solve_finish.argtypes = [vp, i32, vp, vp, vp]
+        L.btd_get_solve_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        L.btd_plan_level_arrays.argtypes = [vp, i32, ctypes.POINTER(LevelArrays)]
         L.btd_residual_work_bytes.argtypes = [i32, i32, i32]
         L.btd_residual_work_bytes.restype = sz
         L.btd_residual.argtypes = [i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp]
@@ -102,10 +112,22 @@ def _stream_handle(stream, device):
     return ctypes.c_void_p(s.cuda_stream)
 
 
-def _aligned_buffer(nbytes, device):
-    """A torch uint8 buffer and a 256-byte-aligned pointer inside it."""
+def _empty_on(stream, *args, **kw):
+    """torch.empty allocated on `stream` (None = the current stream): the
+    caching allocator then reuses the memory only in that stream's order, so
+    a buffer the library's kernels use on `stream` is never handed to other
+    work while they may still run."""
     torch = _torch()
-    buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    if stream is None:
+        return torch.empty(*args, **kw)
+    with torch.cuda.stream(stream):
+        return torch.empty(*args, **kw)
+
+
+def _aligned_buffer(nbytes, device, stream=None):
+    """A torch uint8 buffer (allocated on `stream`) and a 256-byte-aligned pointer inside it."""
+    torch = _torch()
+    buf = _empty_on(stream, nbytes + 256, dtype=torch.uint8, device=device)
     ptr = (buf.data_ptr() + 255) // 256 * 256
     return buf, ptr
 
@@ -175,7 +197,7 @@ class Plan:
         self.device = A.device
         self.A, self.B, self.C = A, B, C
         fbytes, self.solve_bytes = workspace_bytes(N, M, P, depth, max_nrhs, seps, coupling_rows)
-        self._ws, ptr = _aligned_buffer(fbytes, A.device)
+        self._ws, ptr = _aligned_buffer(fbytes, A.device, stream)
         d, _keep = make_desc(N, M, P, depth, max_nrhs, seps, coupling_rows)
         h = ctypes.c_void_p()
         rc = lib().btd_factor(ctypes.byref(d), A.data_ptr(), B.data_ptr(), C.data_ptr(), ptr, fbytes,
@@ -194,15 +216,86 @@ class Plan:
         R = F.shape[2]
         _check(F, "F", (self.N, self.M, R))
         if X is None:
-            X = _torch().empty_like(F)
+            X = _empty_on(stream, F.shape, dtype=F.dtype, device=F.device)
         _check(X, "X", (self.N, self.M, R))
-        buf, ptr = _aligned_buffer(self.solve_bytes, F.device)
+        buf, ptr = _aligned_buffer(self.solve_bytes, F.device, stream)
         rc = lib().btd_solve(self._h, R, F.data_ptr(), X.data_ptr(), ptr, self.solve_bytes,
                              _stream_handle(stream, F.device))
         if rc != BTD_OK:
             raise BtdError(rc, "btd_solve")
         self._last_solve_ws = buf  # lives until the next solve on this plan (stream-ordered reuse)
         return X
+
+    def solve_local(self, F, X=None, Fhat=None, stream=None):
+        """The per-subsystem half of a solve (btd_solve_local): z into the
+        subsystem rows of X and the coupling right-hand side into Fhat
+        ((P-1, M, R)).  Returns (X, Fhat)."""
+        torch = _torch()
+        R = F.shape[2]
+        _check(F, "F", (self.N, self.M, R))
+        if X is None:
+            X = _empty_on(stream, F.shape, dtype=F.dtype, device=F.device)
+        _check(X, "X", (self.N, self.M, R))
+        if Fhat is None and self.P > 1:
+            Fhat = _empty_on(stream, (self.P - 1, self.M, R), dtype=torch.float64, device=F.device)
+        if Fhat is not None:
+            _check(Fhat, "Fhat", (self.P - 1, self.M, R))
+        rc = lib().btd_solve_local(self._h, R, F.data_ptr(), X.data_ptr(),
+                                   Fhat.data_ptr() if Fhat is not None else None, _stream_handle(stream, F.device))
+        if rc != BTD_OK:
+            raise BtdError(rc, "btd_solve_local")
+        return X, Fhat
+
+    def solve_finish(self, H, X, stream=None):
+        """Recovery from the coupling solution H ((P-1, M, R)) into X (btd_solve_finish)."""
+        R = X.shape[2]
+        _check(X, "X", (self.N, self.M, R))
+        if self.P > 1:
+            _check(H, "H", (self.P - 1, self.M, R))
+        rc = lib().btd_solve_finish(self._h, R, H.data_ptr() if H is not None else None, X.data_ptr(),
+                                    _stream_handle(stream, X.device))
+        if rc != BTD_OK:
+            raise BtdError(rc, "btd_solve_finish")
+        return X
+
+    def level_arrays(self, level=0):
+        """Read-only device views of one recursion level (btd_plan_level_arrays)
+        as torch tensors sharing the workspace memory: dict with N, M, P and
+        W (N, M, 2M), Z (N, M, 2M) and Hd, Hb, Hc (P-1, M, M) (None when P = 1)
+        and sep (P+1,)."""
+        torch = _torch()
+        out = LevelArrays()
+        rc = lib().btd_plan_level_arrays(self._h, level, ctypes.byref(out))
+        if rc != BTD_OK:
+            raise BtdError(rc, "btd_plan_level_arrays")
+        N, M, P = out.N, out.M, out.P
+        base = self._ws.data_ptr()
+        u8 = self._ws
+
+        def view(ptr, shape, dtype=torch.float64, esize=8):
+            if not ptr:
+                return None
+            n = 1
+            for d in shape:
+                n *= d
+            off = ptr - base
+            assert 0 <= off and off + n * esize <= u8.numel(), "view outside the factor workspace"
+            return u8[off:off + n * esize].view(dtype).view(*shape)
+
+        return {"N": N, "M": M, "P": P,
+                "W": view(out.W, (N, M, 2 * M)), "Z": view(out.Z, (N, M, 2 * M)),
+                "Hd": view(out.Hd, (P - 1, M, M)), "Hb": view(out.Hb, (P - 1, M, M)),
+                "Hc": view(out.Hc, (P - 1, M, M)), "sep": view(out.sep, (P + 1,), torch.int32, 4)}
+
+    def solve_info(self):
+        """(status, block_row, col) of the right-hand-side check of the last
+        solve; synchronises the device first."""
+        _torch().cuda.synchronize(self.device)
+        st, row, col = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        rc = lib().btd_get_solve_info(self._h, ctypes.byref(st), ctypes.byref(row), ctypes.byref(col))
+        if rc != BTD_OK:
+            raise BtdError(rc, "btd_get_solve_info")
+        return st.value, row.value, col.value
 
     def info(self):
         """(status, block_row, col) of the factor; synchronises the device first."""
@@ -260,9 +353,9 @@ def solve_batch(plans, Fs, Xs=None, stream=None, lanes=1):
     torch = _torch()
     n = len(plans)
     if Xs is None:
-        Xs = [torch.empty_like(F) for F in Fs]
+        Xs = [_empty_on(stream, F.shape, dtype=F.dtype, device=F.device) for F in Fs]
     nbytes = max(lanes, 1) * ((max(p.solve_bytes for p in plans) + 255) // 256 * 256) if n else 256
-    buf, ptr = _aligned_buffer(nbytes, Fs[0].device if n else "cuda")
+    buf, ptr = _aligned_buffer(nbytes, Fs[0].device if n else "cuda", stream)
     hp = (ctypes.c_void_p * max(n, 1))(*[p.handle.value for p in plans])
     nr = (ctypes.c_int32 * max(n, 1))(*[F.shape[2] for F in Fs])
     fp = (ctypes.c_void_p * max(n, 1))(*[F.data_ptr() for F in Fs])
@@ -301,8 +394,9 @@ def residual(A, B, C, X, F, stream=None):
         _check(t, nm, (N, M, M))
     _check(X, "X", (N, M, R))
     _check(F, "F", (N, M, R))
-    out = torch.empty(R, dtype=torch.float64, device=F.device)
-    work = torch.empty(max(lib().btd_residual_work_bytes(N, M, R), 8) // 8, dtype=torch.float64, device=F.device)
+    out = _empty_on(stream, R, dtype=torch.float64, device=F.device)
+    work = _empty_on(stream, max(lib().btd_residual_work_bytes(N, M, R), 8) // 8, dtype=torch.float64,
+                     device=F.device)
     rc = lib().btd_residual(N, M, R, A.data_ptr(), B.data_ptr(), C.data_ptr(), X.data_ptr(), F.data_ptr(),
                             out.data_ptr(), work.data_ptr(), _stream_handle(stream, F.device))
     if rc != BTD_OK:

@@ -61,6 +61,9 @@ hipError_t launch_rhs_fwd_gemm(const KArgs& ka, hipStream_t s);
 hipError_t launch_rhs_getrs(const KArgs& ka, hipStream_t s);
 hipError_t launch_rhs_bwd_gemm(const KArgs& ka, hipStream_t s);
 hipError_t launch_init_status(unsigned long long* st, hipStream_t s);
+// Records in *st the smallest (block row, column) of F [N][M][R] that holds a
+// NaN or an infinity (code BTD_ERR_NONFINITE); *st is left unchanged otherwise.
+hipError_t launch_check_finite(const double* F, int N, int M, int R, unsigned long long* st, hipStream_t s);
 hipError_t launch_write_ints(int* dst, const int* host_vals, int count, hipStream_t s);
 // Partial sums per column of the residual kernels (their work array holds
 // 2 * residual_parts * R doubles).

@@ -2095,6 +2095,19 @@ __global__ void k_init_status(unsigned long long* st) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *st = ~0ULL;
 }
 
+// Non-finite entries of a right-hand side F [N][M][R] (grid-stride, one
+// double per thread and step): each one found reports its (block row,
+// column); the smallest key wins in report_status, so the result does not
+// depend on the schedule.
+__global__ __launch_bounds__(256) void k_check_finite(const double* __restrict__ F, size_t n, int M, int R,
+                                                      unsigned long long* st) {
+    const size_t stride = (size_t)gridDim.x * 256;
+    for (size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x; idx < n; idx += stride) {
+        const double v = F[idx];
+        if (!isfinite(v)) report_status(st, 0, (int)(idx / ((size_t)M * R)), (int)(idx % (size_t)R), BTD_ERR_NONFINITE);
+    }
+}
+
 // sep table of a level: written from kernel arguments (no host-to-device copy)
 __global__ void k_write_ints(int* dst, int count, IntChunk vals) {
     const int t = threadIdx.x;
@@ -2472,6 +2485,13 @@ hipError_t launch_chunk_solve(const KArgs& ka, hipStream_t s) {
 
 hipError_t launch_init_status(unsigned long long* st, hipStream_t s) {
     hipLaunchKernelGGL(k_init_status, dim3(1), dim3(64), 0, s, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_finite(const double* F, int N, int M, int R, unsigned long long* st, hipStream_t s) {
+    const size_t n = (size_t)N * M * R;
+    const int blocks = (int)std::min<size_t>((n + 255) / 256, 2048);
+    hipLaunchKernelGGL(k_check_finite, dim3(blocks), dim3(256), 0, s, F, n, M, R, st);
     return hipGetLastError();
 }
 

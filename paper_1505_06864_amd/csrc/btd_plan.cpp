@@ -9,6 +9,8 @@
 #include <cstring>
 #include <new>
 #include <algorithm>
+#include <atomic>
+#include <mutex>
 #include <vector>
 
 #include "btd_internal.h"
@@ -136,33 +138,61 @@ size_t solve_bytes_for(const std::vector<LevelPlan>& lv, int R) {
     return off > 0 ? off : kAlign;
 }
 
-bool g_configured = false;
-
-// Side streams (default priority) of the current device: the chunks of a
-// level are split into groups whose sweeps run on their own streams, forked
-// from and joined back to the caller's stream with events, so that one
-// group's LU launches overlap the other groups' GEMM and TRSM launches.
+// Side streams (default priority) of each device: the chunks of a level are
+// split into groups whose sweeps run on their own streams, forked from and
+// joined back to the caller's stream with events, so that one group's LU
+// launches overlap the other groups' GEMM and TRSM launches.  The streams
+// are created once per device (under a lock) and shared by every host
+// thread; the fork and join events belong to the calling thread, so the
+// record of one call's fork can never be replaced by another thread's
+// record before the side streams have been told to wait on it.
 constexpr int kMaxGroups = 4;
-struct StreamPool {
-    int device = -1;
+constexpr int kMaxDevices = 16;
+struct SideStreams {
+    std::atomic<bool> ready{false};
     hipStream_t s[kMaxGroups] = {};
+};
+SideStreams g_side[kMaxDevices];
+std::mutex g_side_mu;
+
+struct ThreadEvents {
+    bool ready = false;
     hipEvent_t fork = nullptr, join[kMaxGroups] = {};
 };
-constexpr int kMaxDevices = 16;
-StreamPool g_pools[kMaxDevices];
+thread_local ThreadEvents t_events[kMaxDevices];
 
-StreamPool* stream_pool() {
+struct StreamPool {
+    hipStream_t* s;
+    hipEvent_t fork;
+    hipEvent_t* join;
+};
+
+// Side streams of the current device and the calling thread's events; false
+// when they cannot be created (the caller then runs everything on its own
+// stream).
+bool stream_pool(StreamPool& out) {
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
-    StreamPool& p = g_pools[dev];
-    if (p.device == dev) return &p;
-    for (int g = 0; g < kMaxGroups; ++g) {
-        if (hipStreamCreateWithFlags(&p.s[g], hipStreamNonBlocking) != hipSuccess) return nullptr;
-        if (hipEventCreateWithFlags(&p.join[g], hipEventDisableTiming) != hipSuccess) return nullptr;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return false;
+    SideStreams& side = g_side[dev];
+    if (!side.ready.load(std::memory_order_acquire)) {
+        std::lock_guard<std::mutex> lock(g_side_mu);
+        if (!side.ready.load(std::memory_order_relaxed)) {
+            for (int g = 0; g < kMaxGroups; ++g)
+                if (!side.s[g] && hipStreamCreateWithFlags(&side.s[g], hipStreamNonBlocking) != hipSuccess) return false;
+            side.ready.store(true, std::memory_order_release);
+        }
     }
-    if (hipEventCreateWithFlags(&p.fork, hipEventDisableTiming) != hipSuccess) return nullptr;
-    p.device = dev;
-    return &p;
+    ThreadEvents& ev = t_events[dev];
+    if (!ev.ready) {
+        if (!ev.fork && hipEventCreateWithFlags(&ev.fork, hipEventDisableTiming) != hipSuccess) return false;
+        for (int g = 0; g < kMaxGroups; ++g)
+            if (!ev.join[g] && hipEventCreateWithFlags(&ev.join[g], hipEventDisableTiming) != hipSuccess) return false;
+        ev.ready = true;
+    }
+    out.s = side.s;
+    out.fork = ev.fork;
+    out.join = ev.join;
+    return true;
 }
 
 // Groups for a level of P chunks: at least 8 chunks per group, at most
@@ -170,34 +200,40 @@ StreamPool* stream_pool() {
 // let one group's LU overlap the other's products and triangular solves,
 // more groups starve each other of CUs).
 int chunk_groups(int P) {
-    static int cap = -1;
-    if (cap < 0) {
+    static const int cap = [] {
         const char* env = std::getenv("BTD_STREAM_GROUPS");
         const int v = env ? std::atoi(env) : 0;
-        cap = (v >= 1 && v <= kMaxGroups) ? v : 2;
-    }
+        return (v >= 1 && v <= kMaxGroups) ? v : 2;
+    }();
     int g = P / 8;
     return g < 1 ? 1 : (g > cap ? cap : g);
 }
 
-// Event pairs around the launches of one kernel class (measurement only).
+// Event pairs around the launches of one kernel class (measurement only);
+// the class is read without the lock on every launch, the event list is
+// guarded.
 struct Profiler {
-    int cls = -1;
+    std::atomic<int> cls{-1};
+    std::mutex mu;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
 } g_prof;
 
 hipError_t timed(int cls, hipStream_t s, hipError_t (*fn)(const btd::KArgs&, hipStream_t), const btd::KArgs& ka) {
-    if (g_prof.cls != cls) return fn(ka, s);
+    if (g_prof.cls.load(std::memory_order_relaxed) != cls) return fn(ka, s);
     hipEvent_t a, b;
     if (hipEventCreate(&a) != hipSuccess) return hipErrorUnknown;
     if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return hipErrorUnknown; }
     (void)hipEventRecord(a, s);
     hipError_t err = fn(ka, s);
     (void)hipEventRecord(b, s);
+    std::lock_guard<std::mutex> lock(g_prof.mu);
     g_prof.ev.emplace_back(a, b);
     return err;
 }
 
+// Byte offsets inside the factor workspace: the factor's status word, then
+// the status word of the right-hand-side check of the solves.
+constexpr size_t kFactorStatus = 0, kSolveStatus = 8;
 
 }  // namespace
 
@@ -207,7 +243,8 @@ struct btd_plan_s {
     char* ws = nullptr;
     size_t ws_bytes = 0;
     const double *A = nullptr, *B = nullptr, *C = nullptr;
-    unsigned long long* status = nullptr;
+    unsigned long long* status = nullptr;        // factor status word
+    unsigned long long* solve_status = nullptr;  // right-hand-side check of the last solve
 
     Level level_dev(int l) const {
         const LevelPlan& L = levels[l];
@@ -255,19 +292,19 @@ int enqueue_factor(btd_plan_s* p, hipStream_t s) {
         BTD_TRY(btd::launch_write_ints((int*)(p->ws + LP.off_sep), LP.sep.data(), LP.P + 1, s));
         // chunk groups, each on its own stream (one group: the caller's stream)
         int G = chunk_groups(LP.P);
-        StreamPool* pool = G > 1 ? stream_pool() : nullptr;
-        if (!pool) G = 1;
+        StreamPool pool{};
+        if (G > 1 && !stream_pool(pool)) G = 1;
         hipStream_t gs[kMaxGroups];
         KArgs gk[kMaxGroups];
         for (int g = 0; g < G; ++g) {
-            gs[g] = G > 1 ? pool->s[g] : s;
+            gs[g] = G > 1 ? pool.s[g] : s;
             gk[g] = ka;
             gk[g].c0 = (int)((int64_t)LP.P * g / G);
             gk[g].nc = (int)((int64_t)LP.P * (g + 1) / G) - gk[g].c0;
         }
         if (G > 1) {
-            BTD_TRY(hipEventRecord(pool->fork, s));
-            for (int g = 0; g < G; ++g) BTD_TRY(hipStreamWaitEvent(gs[g], pool->fork, 0));
+            BTD_TRY(hipEventRecord(pool.fork, s));
+            for (int g = 0; g < G; ++g) BTD_TRY(hipStreamWaitEvent(gs[g], pool.fork, 0));
         }
         for (int t = 0; t < LP.nmax; ++t) {
             for (int g = 0; g < G; ++g) {
@@ -287,8 +324,8 @@ int enqueue_factor(btd_plan_s* p, hipStream_t s) {
         }
         if (G > 1) {
             for (int g = 0; g < G; ++g) {
-                BTD_TRY(hipEventRecord(pool->join[g], gs[g]));
-                BTD_TRY(hipStreamWaitEvent(s, pool->join[g], 0));
+                BTD_TRY(hipEventRecord(pool.join[g], gs[g]));
+                BTD_TRY(hipStreamWaitEvent(s, pool.join[g], 0));
             }
         }
         if (LP.P > 1) BTD_TRY(timed(BTD_KC_COUPLE, s, btd::launch_couple, ka));
@@ -296,9 +333,8 @@ int enqueue_factor(btd_plan_s* p, hipStream_t s) {
     return BTD_OK;
 }
 
-// Solve level l in place on X (which already holds F when l > 0).
-int enqueue_solve_level(const btd_plan_s* p, size_t l, int R, const double* F, double* X, char* sws,
-                        size_t sws_off, hipStream_t s) {
+// Right-hand-side sweeps of level l: z on the subsystem rows of X.
+int enqueue_sweep(const btd_plan_s* p, size_t l, int R, const double* F, double* X, hipStream_t s) {
     const LevelPlan& LP = p->levels[l];
     KArgs ka;
     std::memset(&ka, 0, sizeof(ka));
@@ -319,28 +355,83 @@ int enqueue_solve_level(const btd_plan_s* p, size_t l, int R, const double* F, d
             ka.step = t;
             BTD_TRY(timed(BTD_KC_RHS_SWEEP, s, btd::launch_rhs_bwd_gemm, ka));
         }
-        ka.step = 0;
     } else {
         BTD_TRY(timed(BTD_KC_RHS_SWEEP, s, btd::launch_chunk_solve, ka));
-    }
-    if (LP.P > 1) {
-        double* Fc = (double*)(sws + sws_off);
-        const size_t next = align_up(sws_off + sizeof(double) * (size_t)(LP.P - 1) * LP.M * R);
-        ka.Fc = Fc;
-        BTD_TRY(timed(BTD_KC_COUPLE_RHS, s, btd::launch_couple_rhs, ka));
-        int rc = enqueue_solve_level(p, l + 1, R, Fc, Fc, sws, next, s);
-        if (rc != BTD_OK) return rc;
-        BTD_TRY(timed(BTD_KC_RECOVER, s, btd::launch_recover, ka));
     }
     return BTD_OK;
 }
 
-int ensure_configured() {
-    if (!g_configured) {
-        if (btd::configure_kernels() != hipSuccess) return BTD_ERR_LAUNCH;
-        g_configured = true;
+// Coupling right-hand side (Eq. e2311) of level l into Fc, or the recovery
+// (Eq. endSolution) of level l from the coupling solution in Fc.
+int enqueue_couple_rhs(const btd_plan_s* p, size_t l, int R, const double* F, double* X, double* Fc,
+                       hipStream_t s, bool recover) {
+    KArgs ka;
+    std::memset(&ka, 0, sizeof(ka));
+    ka.L = p->level_dev((int)l);
+    ka.R = R;
+    ka.F = F;
+    ka.X = X;
+    ka.Fc = Fc;
+    ka.status = p->status;
+    ka.c0 = 0;
+    ka.nc = p->levels[l].P;
+    if (recover) BTD_TRY(timed(BTD_KC_RECOVER, s, btd::launch_recover, ka));
+    else BTD_TRY(timed(BTD_KC_COUPLE_RHS, s, btd::launch_couple_rhs, ka));
+    return BTD_OK;
+}
+
+// Solve level l in place on X (which already holds F when l > 0).
+int enqueue_solve_level(const btd_plan_s* p, size_t l, int R, const double* F, double* X, char* sws,
+                        size_t sws_off, hipStream_t s) {
+    const LevelPlan& LP = p->levels[l];
+    int rc = enqueue_sweep(p, l, R, F, X, s);
+    if (rc != BTD_OK) return rc;
+    if (LP.P > 1) {
+        double* Fc = (double*)(sws + sws_off);
+        const size_t next = align_up(sws_off + sizeof(double) * (size_t)(LP.P - 1) * LP.M * R);
+        rc = enqueue_couple_rhs(p, l, R, F, X, Fc, s, false);
+        if (rc != BTD_OK) return rc;
+        rc = enqueue_solve_level(p, l + 1, R, Fc, Fc, sws, next, s);
+        if (rc != BTD_OK) return rc;
+        rc = enqueue_couple_rhs(p, l, R, F, X, Fc, s, true);
+        if (rc != BTD_OK) return rc;
     }
     return BTD_OK;
+}
+
+// The check of the right-hand side every solve starts with (non-finite
+// entries of F, reported by btd_get_solve_info).
+int enqueue_rhs_check(const btd_plan_s* p, int R, const double* F, hipStream_t s) {
+    BTD_TRY(btd::launch_init_status(p->solve_status, s));
+    BTD_TRY(btd::launch_check_finite(F, p->desc.N, p->desc.M, R, p->solve_status, s));
+    return BTD_OK;
+}
+
+// A status word (level, row, col, code) read back from the device.
+int read_status(const btd_plan_s* p, const unsigned long long* word, int32_t* status, int32_t* block_row,
+                int32_t* col) {
+    unsigned long long key = ~0ULL;
+    if (hipMemcpy(&key, word, sizeof(key), hipMemcpyDeviceToHost) != hipSuccess) return BTD_ERR_LAUNCH;
+    int st = BTD_OK, row = -1, c = -1;
+    if (key != ~0ULL) {
+        const int level = (int)(key >> 56);
+        row = (int)((key >> 32) & 0xffffff);
+        c = (int)((key >> 8) & 0xffffff);
+        st = (int)(key & 0xff);
+        // map a coupling-system row back to the separator row of the level above
+        for (int l = level; l > 0; --l) row = p->levels[l - 1].sep[row + 1];
+    }
+    if (status) *status = st;
+    if (block_row) *block_row = row;
+    if (col) *col = c;
+    return BTD_OK;
+}
+
+int ensure_configured() {
+    static std::once_flag once;
+    static hipError_t err = hipSuccess;
+    std::call_once(once, [] { err = btd::configure_kernels(); });
+    return err == hipSuccess ? BTD_OK : BTD_ERR_LAUNCH;
 }
 
 }  // namespace
@@ -384,7 +475,8 @@ int btd_factor(const btd_desc_t* desc, const double* A, const double* B, const d
     p->ws = (char*)factor_ws;
     p->ws_bytes = factor_bytes;
     p->A = A; p->B = B; p->C = C;
-    p->status = (unsigned long long*)factor_ws;
+    p->status = (unsigned long long*)((char*)factor_ws + kFactorStatus);
+    p->solve_status = (unsigned long long*)((char*)factor_ws + kSolveStatus);
     rc = enqueue_factor(p, (hipStream_t)stream);
     if (rc != BTD_OK) { delete p; return rc; }
     *out = p;
@@ -402,7 +494,59 @@ int btd_solve(btd_plan_t plan, int32_t nrhs, const double* F, double* X, void* s
     if (solve_bytes < need) return -6;
     int rc = ensure_configured();
     if (rc != BTD_OK) return rc;
+    rc = enqueue_rhs_check(plan, nrhs, F, (hipStream_t)stream);
+    if (rc != BTD_OK) return rc;
     return enqueue_solve_level(plan, 0, nrhs, F, X, (char*)solve_ws, 0, (hipStream_t)stream);
+}
+
+int btd_solve_local(btd_plan_t plan, int32_t nrhs, const double* F, double* X, double* Fhat, void* stream) {
+    if (!plan) return -1;
+    if (nrhs < 1 || nrhs > plan->desc.max_nrhs) return -2;
+    if (!F) return -3;
+    if (!X) return -4;
+    if (plan->levels[0].P > 1 && !Fhat) return -5;
+    int rc = ensure_configured();
+    if (rc != BTD_OK) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    rc = enqueue_rhs_check(plan, nrhs, F, s);
+    if (rc != BTD_OK) return rc;
+    rc = enqueue_sweep(plan, 0, nrhs, F, X, s);
+    if (rc != BTD_OK || plan->levels[0].P == 1) return rc;
+    return enqueue_couple_rhs(plan, 0, nrhs, F, X, Fhat, s, false);
+}
+
+int btd_solve_finish(btd_plan_t plan, int32_t nrhs, const double* H, double* X, void* stream) {
+    if (!plan) return -1;
+    if (nrhs < 1 || nrhs > plan->desc.max_nrhs) return -2;
+    if (plan->levels[0].P > 1 && !H) return -3;
+    if (!X) return -4;
+    if (plan->levels[0].P == 1) return BTD_OK;
+    int rc = ensure_configured();
+    if (rc != BTD_OK) return rc;
+    return enqueue_couple_rhs(plan, 0, nrhs, nullptr, X, const_cast<double*>(H), (hipStream_t)stream, true);
+}
+
+int btd_get_solve_info(btd_plan_t plan, int32_t* status, int32_t* block_row, int32_t* col) {
+    if (!plan) return -1;
+    return read_status(plan, plan->solve_status, status, block_row, col);
+}
+
+int btd_plan_level_arrays(btd_plan_t plan, int32_t level, btd_level_arrays_t* out) {
+    if (!plan || !out || level < 0 || level >= (int)plan->levels.size()) return -1;
+    const Level d = plan->level_dev(level);
+    out->N = d.N;
+    out->M = d.M;
+    out->P = d.P;
+    out->A = d.A;
+    out->B = d.B;
+    out->C = d.C;
+    out->W = d.W;
+    out->Z = d.Z;
+    out->Hd = d.Hd;
+    out->Hb = d.Hb;
+    out->Hc = d.Hc;
+    out->sep = d.sep;
+    return BTD_OK;
 }
 
 int btd_solve_batch(int32_t count, const btd_plan_t* plans, const int32_t* nrhs, const double* const* F,
@@ -420,15 +564,21 @@ int btd_solve_batch(int32_t count, const btd_plan_t* plans, const int32_t* nrhs,
         if (!solve_ws || ((uintptr_t)solve_ws % kAlign) != 0 || solve_bytes < need) return -6;
     }
     if (count == 0) return BTD_OK;
+    int rc0 = ensure_configured();
+    if (rc0 != BTD_OK) return rc0;
     hipStream_t s0 = (hipStream_t)stream;
+    for (int s = 0; s < count; ++s) {
+        int rc = enqueue_rhs_check(plans[s], nrhs[s], F[s], s0);
+        if (rc != BTD_OK) return rc;
+    }
     // with room for k solves in solve_ws, up to k of them run side by side on
     // the library's side streams, each in its own slice of the workspace
     size_t need = 0;
     for (int s = 0; s < count; ++s) need = std::max(need, solve_bytes_for(plans[s]->levels, nrhs[s]));
     const size_t slice = align_up(need);
     int lanes = (int)std::min<size_t>({solve_bytes / slice, (size_t)kMaxGroups, (size_t)count});
-    StreamPool* pool = lanes > 1 ? stream_pool() : nullptr;
-    if (!pool) lanes = 1;
+    StreamPool pool{};
+    if (lanes > 1 && !stream_pool(pool)) lanes = 1;
     if (lanes == 1) {
         for (int s = 0; s < count; ++s) {
             int rc = enqueue_solve_level(plans[s], 0, nrhs[s], F[s], X[s], (char*)solve_ws, 0, s0);
@@ -436,17 +586,17 @@ int btd_solve_batch(int32_t count, const btd_plan_t* plans, const int32_t* nrhs,
         }
         return BTD_OK;
     }
-    BTD_TRY(hipEventRecord(pool->fork, s0));
-    for (int g = 0; g < lanes; ++g) BTD_TRY(hipStreamWaitEvent(pool->s[g], pool->fork, 0));
+    BTD_TRY(hipEventRecord(pool.fork, s0));
+    for (int g = 0; g < lanes; ++g) BTD_TRY(hipStreamWaitEvent(pool.s[g], pool.fork, 0));
     for (int s = 0; s < count; ++s) {
         const int g = s % lanes;
         int rc = enqueue_solve_level(plans[s], 0, nrhs[s], F[s], X[s], (char*)solve_ws + (size_t)g * slice, 0,
-                                     pool->s[g]);
+                                     pool.s[g]);
         if (rc != BTD_OK) return rc;
     }
     for (int g = 0; g < lanes; ++g) {
-        BTD_TRY(hipEventRecord(pool->join[g], pool->s[g]));
-        BTD_TRY(hipStreamWaitEvent(s0, pool->join[g], 0));
+        BTD_TRY(hipEventRecord(pool.join[g], pool.s[g]));
+        BTD_TRY(hipStreamWaitEvent(s0, pool.join[g], 0));
     }
     return BTD_OK;
 }
@@ -468,13 +618,14 @@ int btd_residual(int32_t N, int32_t M, int32_t R, const double* A, const double*
     if (!work) return -10;
     hipStream_t s = (hipStream_t)stream;
     hipEvent_t a = nullptr, b = nullptr;
-    if (g_prof.cls == BTD_KC_RESIDUAL) {
+    if (g_prof.cls.load(std::memory_order_relaxed) == BTD_KC_RESIDUAL) {
         if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return BTD_ERR_LAUNCH;
         (void)hipEventRecord(a, s);
     }
     BTD_TRY(btd::launch_residual(N, M, R, A, B, C, X, F, out, (double*)work, s));
     if (a) {
         (void)hipEventRecord(b, s);
+        std::lock_guard<std::mutex> lock(g_prof.mu);
         g_prof.ev.emplace_back(a, b);
     }
     return BTD_OK;
@@ -482,21 +633,7 @@ int btd_residual(int32_t N, int32_t M, int32_t R, const double* A, const double*
 
 int btd_get_info(btd_plan_t plan, int32_t* status, int32_t* block_row, int32_t* col) {
     if (!plan) return -1;
-    unsigned long long key = ~0ULL;
-    if (hipMemcpy(&key, plan->status, sizeof(key), hipMemcpyDeviceToHost) != hipSuccess) return BTD_ERR_LAUNCH;
-    int st = BTD_OK, row = -1, c = -1;
-    if (key != ~0ULL) {
-        const int level = (int)(key >> 56);
-        row = (int)((key >> 32) & 0xffffff);
-        c = (int)((key >> 8) & 0xffffff);
-        st = (int)(key & 0xff);
-        // map a coupling-system row back to the separator row of the level above
-        for (int l = level; l > 0; --l) row = plan->levels[l - 1].sep[row + 1];
-    }
-    if (status) *status = st;
-    if (block_row) *block_row = row;
-    if (col) *col = c;
-    return BTD_OK;
+    return read_status(plan, plan->status, status, block_row, col);
 }
 
 int btd_plan_separators(btd_plan_t plan, int32_t* seps_out) {
@@ -563,7 +700,7 @@ int btd_coupling_parts(int32_t P, int32_t M, int32_t R, int32_t coupling_rows) {
 
 int btd_profile_enable(int32_t kernel_class) {
     if (kernel_class < -1 || kernel_class >= BTD_KC_COUNT) return -1;
-    g_prof.cls = kernel_class;
+    g_prof.cls.store(kernel_class);
     return BTD_OK;
 }
 
@@ -571,6 +708,7 @@ int btd_profile_read(double* total_ms, int64_t* launches) {
     double tot = 0.0;
     int64_t n = 0;
     int rc = BTD_OK;
+    std::lock_guard<std::mutex> lock(g_prof.mu);
     for (auto& pr : g_prof.ev) {
         float ms = 0.0f;
         if (hipEventSynchronize(pr.second) != hipSuccess || hipEventElapsedTime(&ms, pr.first, pr.second) != hipSuccess)

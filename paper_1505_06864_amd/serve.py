@@ -50,6 +50,7 @@ class Server:
         self.running = {}                                # slot -> (request, event, solve bytes)
         self.resident = collections.OrderedDict()        # key -> [plan, bytes, running solves, factored event]
         self.used = 0
+        self.peak = 0
         self.evictions = 0
 
     def _need(self, req):
@@ -58,9 +59,12 @@ class Server:
         fbytes, sbytes = btd.workspace_bytes(N, M, P, DEPTH, MAX_NRHS, None, COUPLING_ROWS)
         return (0 if req.key in self.resident else fbytes), sbytes
 
-    def _make_room(self, need):
+    def _make_room(self, need, keep=None):
+        """Evict idle resident factorizations, least recently used first, until
+        `need` more bytes fit; `keep` (the system the request reuses) is never
+        evicted."""
         while self.used + need > self.budget:
-            victim = next((k for k, v in self.resident.items() if v[2] == 0), None)
+            victim = next((k for k, v in self.resident.items() if v[2] == 0 and k != keep), None)
             if victim is None:
                 return False
             plan, nbytes = self.resident.pop(victim)[:2]
@@ -76,7 +80,7 @@ class Server:
         if slot is None:
             return False
         fneed, sneed = self._need(req)
-        if fneed + sneed > self.budget or not self._make_room(fneed + sneed):
+        if fneed + sneed > self.budget or not self._make_room(fneed + sneed, keep=req.key):
             return False
         s = self.streams[slot]
         torch = self.torch
@@ -99,6 +103,8 @@ class Server:
             ev = torch.cuda.Event()
             ev.record(s)
         self.used += sneed
+        assert self.used <= self.budget, (self.used, self.budget)
+        self.peak = max(self.peak, self.used)
         req.t_start = now
         self.running[slot] = (req, ev, sneed)
         return True
@@ -141,7 +147,7 @@ def serve(requests, budget_bytes, slots=4, keep_results=False):
             waiting.popleft()
         if not srv.running and waiting:
             raise RuntimeError(f"request {waiting[0].rid} does not fit the budget")
-    counters = {"evictions": srv.evictions,
+    counters = {"evictions": srv.evictions, "peak_bytes": srv.peak,
                 "factored": sum(r.factored for r in finished),
                 "reused": sum(not r.factored for r in finished)}
     srv.close()

@@ -328,12 +328,95 @@ def test_costmodel_printed_example():
     assert (round(M), round(J), round(m)) == (g["M"], g["J"], g["m"])
 
 
-def test_speedup_formula_properties():
-    N, n = 3071, 400
+def _weighted(cnt, n, l):
+    """A count of the operation counter in multiplicative operations for block
+    size n and l right-hand-side columns (Sec. 4 units)."""
+    return (cnt["inv"] + cnt["mm"]) * n**3 + cnt["mr"] * n**2 * l
+
+
+def _count_ta(N):
+    A, B, C, F = rand_system(N, 2, 1, seed=50 + N)
+    cnt = oracle.Counter()
+    oracle.ta_solve(A, B, C, F, counter=cnt)
+    return cnt.as_dict()
+
+
+def _count_dm(sizes):
+    """Operation counter of the method on a system with the given subsystem sizes."""
+    P = len(sizes)
+    seps, pos = [], 0
+    for x in sizes[:-1]:
+        pos += x
+        seps.append(pos)
+        pos += 1
+    N = sum(sizes) + P - 1
+    A, B, C, F = rand_system(N, 2, 1, seed=60 + N)
+    cnt = oracle.Counter()
+    oracle.dm_solve(A, B, C, F, P, seps=seps, counter=cnt)
+    return cnt.as_dict()
+
+
+def _serial_middle(Nk, n, l):
+    """Multiplicative operations of one middle subsystem of Nk rows (its
+    solve of Eq. e231, its share of the coupling products and of the
+    recovery), taken from the operation counter: a method run with
+    subsystems (2, Nk, 3) minus a run with (2, 3) counts the middle subsystem
+    plus the growth of the coupling Thomas algorithm from one to two rows."""
+    w3 = _weighted(_count_dm([2, Nk, 3]), n, l)
+    w2 = _weighted(_count_dm([2, 3]), n, l)
+    return w3 - w2 - (_weighted(_count_ta(2), n, l) - _weighted(_count_ta(1), n, l))
+
+
+@pytest.mark.parametrize("n,l", [(400, 1), (100, 37), (3, 8)])
+def test_speedup_mp_matches_counted_operations(n, l):
+    """Eq. SpeedupMP is the Thomas algorithm's operations over the serial
+    operations of the method with P equal subsystems: one middle subsystem
+    plus the coupling system of P-1 rows by the Thomas algorithm (Sec. 5.1).
+    Both are built from the operation counter (pinned to Tab. 1 and Tab. 2);
+    n and l enter with different powers, so a swapped l/n fails."""
+    for Nk, P in [(4, 3), (7, 5), (12, 9), (30, 17)]:
+        N = P * Nk + P - 1
+        ta = _weighted(_count_ta(N), n, l)
+        serial = _serial_middle(Nk, n, l) + _weighted(_count_ta(P - 1), n, l)
+        assert np.isclose(costmodel.speedup_mp(N, P, n, l), ta / serial, rtol=1e-13, atol=0)
+    N = 3071
     for P in range(2, 300):
-        S = costmodel.speedup_mp(N, P, n, 1)
-        assert S > costmodel.speedup_mp_lower(N, P)
-        # the DM total of Eq. DMtotal with equal subsystems reproduces Eq. SpeedupMP for l = n
-    Popt = costmodel.speedup_optimal_P(N, n, 1)
-    s = [costmodel.speedup_mp(N, P, n, 1) for P in (Popt - 5, Popt, Popt + 5)]
-    assert s[1] > s[0] and s[1] > s[2]
+        assert costmodel.speedup_mp(N, P, n, l) > costmodel.speedup_mp_lower(N, P)
+    # linear growth S ~ 3P/7 for P << N and l << n, as stated after Eq. SpeedupMP
+    assert np.isclose(costmodel.speedup_mp(10**9, 10, 10**6, 1) / (3 * 10 / 7), 1.0, rtol=1e-4)
+
+
+def test_speedup_maximiser_is_the_counted_optimum():
+    """Eq. MAXSpeedP is the maximiser of Eq. SpeedupMP (checked on a fine
+    grid of real P) and reduces to sqrt(7(N+1)/3) for l << n (Sec. 5.1)."""
+    N = 3071
+    for n, l in [(400, 1), (100, 100), (50, 400)]:
+        Popt = costmodel.speedup_optimal_P(N, n, l)
+        grid = np.linspace(2.0, 600.0, 600001)
+        best = grid[np.argmax(costmodel.speedup_mp(N, grid, n, l))]
+        assert abs(best - Popt) < 2e-3
+    assert np.isclose(costmodel.speedup_optimal_P(N, 10**9, 1), np.sqrt(7 * (N + 1) / 3), rtol=1e-8)
+
+
+@pytest.mark.parametrize("n,l", [(400, 1), (64, 64), (16, 200)])
+def test_suppmatr_m_minimises_counted_operations(n, l):
+    """Eq. SuppMatrM minimises the serial operations of Eq. DMrec2: a middle
+    subsystem of N1 rows, a middle coupling subsystem of (P-m)/m rows and the
+    Thomas algorithm on the m-1 separators of the coupling system.  Every
+    term is taken from the operation counter; a middle subsystem's count is
+    linear in its rows (checked), so it extends to fractional sizes."""
+    per_row = _serial_middle(1, n, l)
+    for Nk in (2, 5, 11):
+        assert _serial_middle(Nk, n, l) == Nk * per_row
+    ta = {k: _weighted(_count_ta(k), n, l) for k in (1, 2)}
+    ta_row = ta[2] - ta[1]                 # Tab. 1: (3k-2) is linear in k
+    for P in (30, 64, 256, 1000):
+        m = np.linspace(2.0, P / 3.0, 200001)
+        serial = ((P - m) / m) * per_row + (ta[1] + (m - 2) * ta_row)
+        best = m[np.argmin(serial)]
+        assert abs(best - costmodel.suppmatr_m(P, n, l)) < 1e-2 * max(1.0, best / 10)
+    # the statements that follow Eq. SuppMatrM: m ~ sqrt(7P/3) for l << n,
+    # and the requirement (P-m)/m >= 2 holds exactly from P = 21 on
+    assert np.isclose(costmodel.suppmatr_m(300, 10**9, 1), np.sqrt(7 * 300 / 3), rtol=1e-8)
+    assert np.isclose(3 * costmodel.suppmatr_m(21, 10**9, 0), 21.0, rtol=1e-12)
+    assert 3 * costmodel.suppmatr_m(20, 10**9, 0) > 20.0
