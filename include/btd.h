@@ -60,6 +60,7 @@ extern "C" {
 #define BTD_ERR_SINGULAR 1   /* an exactly zero pivot in the LU of a diagonal block D_i */
 #define BTD_ERR_NONFINITE 2  /* a pivot that is NaN or infinite                          */
 #define BTD_ERR_LAUNCH 3     /* a HIP launch or copy failed (returned by the call)       */
+#define BTD_ERR_SCRATCH 4    /* btd_solve_noalloc: the solve needs more than the static scratch */
 
 #define BTD_PREC_F64 0
 
@@ -158,6 +159,25 @@ int btd_solve(btd_plan_t plan, int32_t nrhs, const double *F, double *X, void *s
 int btd_solve_batch(int32_t count, const btd_plan_t *plans, const int32_t *nrhs,
                     const double *const *F, double *const *X, void *solve_ws, size_t solve_bytes,
                     void *stream);
+
+/*
+ * btd_solve without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  The same computation and kernels as
+ * btd_solve; its scratch (the coupling right-hand sides of every recursion
+ * level) is a static device array of BTD_NOALLOC_SCRATCH_BYTES that the
+ * library holds on each device it runs on until the process ends.  The call
+ * allocates nothing.  Every call on one device shares that device's array:
+ * calls that overlap on one device (two streams, or two host threads) race
+ * and give wrong results; serialise them.  The array keeps the last call's
+ * contents, none of which a later call reads before writing it.
+ * Returns 0; -1 NULL plan; -2 nrhs out of range; -3/-4 NULL F/X;
+ * BTD_ERR_SCRATCH when btd_workspace_bytes' solve size for this plan and
+ * nrhs exceeds BTD_NOALLOC_SCRATCH_BYTES (nothing is enqueued; use btd_solve);
+ * BTD_ERR_LAUNCH.
+ */
+#define BTD_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int btd_solve_noalloc(btd_plan_t plan, int32_t nrhs, const double *F, double *X, void *stream);
 
 /*
  * The two halves of btd_solve, for a caller that solves the coupling system

@@ -16,12 +16,13 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbtd.so")
 
-BTD_OK, BTD_ERR_SINGULAR, BTD_ERR_NONFINITE, BTD_ERR_LAUNCH = 0, 1, 2, 3
+BTD_OK, BTD_ERR_SINGULAR, BTD_ERR_NONFINITE, BTD_ERR_LAUNCH, BTD_ERR_SCRATCH = 0, 1, 2, 3, 4
+NOALLOC_SCRATCH_BYTES = 64 << 20
 BTD_PREC_F64 = 0
 BTD_MAX_M = 512
 
 # Every symbol include/btd.h declares.
-EXPORTS = ("btd_workspace_bytes", "btd_factor", "btd_solve", "btd_solve_batch", "btd_solve_local",
+EXPORTS = ("btd_workspace_bytes", "btd_factor", "btd_solve", "btd_solve_batch", "btd_solve_noalloc", "btd_solve_local",
            "btd_solve_finish", "btd_get_solve_info", "btd_plan_level_arrays", "btd_residual_work_bytes",
            "btd_residual", "btd_get_info", "btd_plan_separators", "btd_plan_level_parts",
            "btd_default_separators", "btd_balanced_separators", "btd_default_coupling_parts",
@@ -60,6 +61,7 @@ def lib():
         L.btd_solve.argtypes = [vp, i32, vp, vp, vp, sz, vp]
         L.btd_solve_batch.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(i32), ctypes.POINTER(vp),
                                       ctypes.POINTER(vp), vp, sz, vp]
+        L.btd_solve_noalloc.argtypes = [vp, i32, vp, vp, vp]
         L.btd_solve_local.argtypes = [vp, i32, vp, vp, vp, vp]
         L.btd_solve_finish.argtypes = [vp, i32, vp, vp, vp]
         L.btd_get_solve_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]

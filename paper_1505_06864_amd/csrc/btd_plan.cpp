@@ -231,6 +231,32 @@ hipError_t timed(int cls, hipStream_t s, hipError_t (*fn)(const btd::KArgs&, hip
     return err;
 }
 
+// Scratch of btd_solve_noalloc: a static device array (one copy per device
+// the library runs on, held until the process ends).  In host code its name
+// is only a host-side stand-in, so its device address is taken once per
+// device with hipGetSymbolAddress (with that device current) and only that
+// address is passed to kernels.
+static __device__ __align__(256) char scratch[BTD_NOALLOC_SCRATCH_BYTES];
+std::atomic<char*> g_scratch_ptr[kMaxDevices];
+std::mutex g_scratch_mu;
+
+// Device address of the current device's scratch, or nullptr on failure.
+char* scratch_ptr() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    char* p = g_scratch_ptr[dev].load(std::memory_order_acquire);
+    if (p) return p;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    p = g_scratch_ptr[dev].load(std::memory_order_relaxed);
+    if (!p) {
+        void* addr = nullptr;
+        if (hipGetSymbolAddress(&addr, HIP_SYMBOL(scratch)) != hipSuccess || !addr) return nullptr;
+        p = (char*)addr;
+        g_scratch_ptr[dev].store(p, std::memory_order_release);
+    }
+    return p;
+}
+
 // Byte offsets inside the factor workspace: the factor's status word, then
 // the status word of the right-hand-side check of the solves.
 constexpr size_t kFactorStatus = 0, kSolveStatus = 8;
@@ -499,6 +525,22 @@ int btd_solve(btd_plan_t plan, int32_t nrhs, const double* F, double* X, void* s
     return enqueue_solve_level(plan, 0, nrhs, F, X, (char*)solve_ws, 0, (hipStream_t)stream);
 }
 
+int btd_solve_noalloc(btd_plan_t plan, int32_t nrhs, const double* F, double* X, void* stream) {
+    if (!plan) return -1;
+    if (nrhs < 1 || nrhs > plan->desc.max_nrhs) return -2;
+    if (!F) return -3;
+    if (!X) return -4;
+    if (solve_bytes_for(plan->levels, nrhs) > BTD_NOALLOC_SCRATCH_BYTES) return BTD_ERR_SCRATCH;
+    int rc = ensure_configured();
+    if (rc != BTD_OK) return rc;
+    char* ws = scratch_ptr();
+    if (!ws) return BTD_ERR_LAUNCH;
+    hipStream_t s = (hipStream_t)stream;
+    rc = enqueue_rhs_check(plan, nrhs, F, s);
+    if (rc != BTD_OK) return rc;
+    return enqueue_solve_level(plan, 0, nrhs, F, X, ws, 0, s);
+}
+
 int btd_solve_local(btd_plan_t plan, int32_t nrhs, const double* F, double* X, double* Fhat, void* stream) {
     if (!plan) return -1;
     if (nrhs < 1 || nrhs > plan->desc.max_nrhs) return -2;
@@ -736,6 +778,7 @@ const char* btd_status_string(int code) {
         case BTD_ERR_SINGULAR: return "exactly zero pivot in the LU of a diagonal block";
         case BTD_ERR_NONFINITE: return "non-finite pivot in the LU of a diagonal block";
         case BTD_ERR_LAUNCH: return "HIP launch or copy failed";
+        case BTD_ERR_SCRATCH: return "solve needs more scratch than the static buffer of btd_solve_noalloc";
         default: return code < 0 ? "invalid argument" : "unknown status";
     }
 }
