@@ -56,6 +56,13 @@ def parse():
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB three times (calibrates "
                          "the HBM byte counters against a kernel of known traffic) and exit")
+    ap.add_argument("--prec", choices=("f64", "f32_refine"), default="f64",
+                    help="f32_refine: factor products on FP32 MFMA, then iterative refinement to residual 1e-12 "
+                         "(FP64 residual, correction and coupling systems); the step is factor + refined solve")
+    ap.add_argument("--sweep", choices=("faddeev", "P"), default=None,
+                    help="instead of the benchmark line: 'faddeev' times the Faddeev-type workload at P in "
+                         "{8, 32, 128, 512} x depth {0, 1} (Eq. SuppMatrM coupling split), 'P' the large "
+                         "workload at P in {128, 256, 512, 1024} and the split choices; one JSON line each")
     return ap.parse_args()
 
 
@@ -88,7 +95,7 @@ def make_inputs(torch, name, dev):
 class Runner:
     """Direct C-ABI calls with preallocated workspaces (no allocation per step)."""
 
-    def __init__(self, torch, A, B, C, F, P, depth, coupling_rows=0, seps=None):
+    def __init__(self, torch, A, B, C, F, P, depth, coupling_rows=0, seps=None, prec="f64"):
         import ctypes
         from paper_1505_06864_amd import btd
         self.ct, self.btd, self.torch = ctypes, btd, torch
@@ -96,7 +103,8 @@ class Runner:
         self.N, self.M, _ = A.shape
         self.R = F.shape[2]
         self.A, self.B, self.C, self.F = A, B, C, F
-        self.desc, self._keep = btd.make_desc(self.N, self.M, P, depth, self.R, seps, coupling_rows)
+        self.prec = prec
+        self.desc, self._keep = btd.make_desc(self.N, self.M, P, depth, self.R, seps, coupling_rows, prec)
         fb, sb = btd.workspace_bytes(self.N, self.M, P, depth, self.R, seps, coupling_rows)
         self.fws, self.fptr = btd._aligned_buffer(fb, A.device)
         self.sws, self.sptr = btd._aligned_buffer(sb, A.device)
@@ -108,6 +116,8 @@ class Runner:
         self.stream = torch.cuda.current_stream(A.device)
         self.sh = ctypes.c_void_p(self.stream.cuda_stream)
         self.plans = []
+        self.iters = []
+        self.refine_res = []
 
     def use_stream(self, stream):
         self.stream = stream
@@ -135,6 +145,22 @@ class Runner:
                           self.fptr, self.fb, self.sh, ct.byref(h))
         if rc:
             raise self.btd.BtdError(rc, "btd_factor")
+        if self.prec == "f32_refine":
+            # refined solve: the FP64 residual (and its norms) is part of every iteration
+            if not hasattr(self, "rws"):
+                nb = L.btd_refine_work_bytes(h, self.R)
+                self.rws, self.rptr = self.btd._aligned_buffer(nb, self.A.device)
+                self.rb = nb
+            it, res = ct.c_int32(), ct.c_double()
+            rc = L.btd_solve_refine(h, self.R, self.F.data_ptr(), self.X.data_ptr(), self.rptr, self.rb,
+                                    ct.c_double(1e-12), 8, ct.byref(it), ct.byref(res), self.sh)
+            if rc:
+                raise self.btd.BtdError(rc, "btd_solve_refine")
+            self.iters.append(it.value)
+            self.refine_res.append(res.value)
+            self.res.fill_(res.value)
+            self.plans.append(h)
+            return
         rc = L.btd_solve(h, self.R, self.F.data_ptr(), self.X.data_ptr(), self.sptr, self.sb, self.sh)
         if rc:
             raise self.btd.BtdError(rc, "btd_solve")
@@ -209,11 +235,25 @@ def breakdown(torch, run, A, B, C, F, ms_step, reps=5):
                     "with P = 1 (one subsystem), timed once; speedup = TA time / DM time per solve"}
 
 
-def cpu_baseline(host_inputs, P, depth, rows, workload):
+def host_cpu():
+    """(CPU model, logical CPUs) of the host."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model, os.cpu_count()
+
+
+def cpu_baseline(host_inputs, P, gpu_depth, gpu_crow, rows, workload):
     """The oracle, as it stands, on a bounded sample: the first `rows` block
-    rows of the same workload (its own subsystem count scaled with the
-    rows), timed on the host; converted to solves/s of the full workload by
-    the ratio of algorithmic FLOPs."""
+    rows of the same workload split into subsystems of the GPU plan's size
+    (so the per-row work is the same), one recursion level on the coupling
+    system, timed on the host; converted to solves/s of the full workload by
+    the ratio of algorithmic FLOPs (about the ratio of rows)."""
     import numpy as np
 
     import oracle
@@ -221,20 +261,26 @@ def cpu_baseline(host_inputs, P, depth, rows, workload):
     A, B, C, F = host_inputs
     N, M, R = F.shape
     rows = min(rows, N)
+    chunk = max(1, (N - P + 1) // P)                 # rows per subsystem in the GPU plan
+    Ps = max(1, (rows + 1) // (chunk + 1))
+    depth = 1 if Ps >= 4 else 0
     threads = oracle.max_threads()
-    Ps = max(1, min(threads, rows // 3))
     As, Bs, Cs = (np.ascontiguousarray(x[:rows]) for x in (A, B, C))
     Fs = np.ascontiguousarray(F[:rows])
     t0 = time.perf_counter()
-    oracle.dm_solve(As, Bs, Cs, Fs, Ps, depth=depth if Ps >= 4 else 0, nthreads=threads)
+    oracle.dm_solve(As, Bs, Cs, Fs, Ps, depth=depth, nthreads=threads)
     dt = time.perf_counter() - t0
-    f_s = sum(flops.totals(rows, M, R, Ps, depth if Ps >= 4 else 0))
-    f_full = sum(flops.totals(N, M, R, P, depth))
+    f_s = sum(flops.totals(rows, M, R, Ps, depth))
+    f_full = sum(flops.totals(N, M, R, P, gpu_depth, R, None, gpu_crow))
     t_full = dt * f_full / f_s
+    model, ncpu = host_cpu()
     return {"value": 1.0 / t_full, "unit": "solves/s", "cores": min(threads, Ps), "kind": "oracle",
-            "sample": (f"oracle DM (FP64, explicit block inverses, OpenMP over subsystems) on the first {rows} "
-                       f"block rows of the {workload} workload (M={M}, R={R}, P={Ps}); {dt:.2f} s measured, "
-                       f"scaled to the full workload by the algorithmic-FLOP ratio {f_full / f_s:.1f}")}
+            "cpu_model": model, "host_logical_cpus": ncpu,
+            "sample": (f"oracle DM (FP64, explicit block inverses, OpenMP over subsystems, {min(threads, Ps)} "
+                       f"threads) on the first {rows} block rows of the {workload} workload (M={M}, R={R}) in "
+                       f"{Ps} subsystems of about {chunk} rows like the GPU plan, one recursion level on the "
+                       f"coupling system; {dt:.2f} s measured, scaled to the full workload by the "
+                       f"algorithmic-FLOP ratio {f_full / f_s:.2f}")}
 
 
 def recorded_traffic(kclass, workload, P, depth, coupling_rows):
@@ -260,6 +306,48 @@ def recorded_traffic(kclass, workload, P, depth, coupling_rows):
     return float(kv["hbm_bytes_per_launch"])
 
 
+def time_steps(torch, run, steps, warmup=2):
+    """ms per whole step (factor, solve, residual) over `steps` steps, no
+    profiling events."""
+    for _ in range(warmup):
+        run.step()
+    torch.cuda.synchronize()
+    run.release()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        run.step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    resid = float(run.res.max().item())
+    run.release()
+    return ms, resid
+
+
+def sweep(torch, args):
+    """One JSON line per configuration (not the benchmark line)."""
+    from paper_1505_06864_amd import flops
+    dev = torch.device("cuda:0")
+    if args.sweep == "faddeev":
+        (A, B, C, F), _ = make_inputs(torch, "faddeev", dev)
+        configs = [(P, d, 0) for P in (8, 32, 128, 512) for d in (0, 1)]
+        name = "faddeev"
+    else:
+        (A, B, C, F), _ = make_inputs(torch, "large", dev)
+        configs = [(P, DEFAULT_DEPTH, 1) for P in (128, 256, 512, 1024)] + [(256, 1, 0), (256, 10, 0), (64, 1, 0)]
+        name = "large"
+    N, M, R = F.shape
+    for P, depth, crow in configs:
+        run = Runner(torch, A, B, C, F, P, depth, crow)
+        ms, resid = time_steps(torch, run, args.steps)
+        fl = sum(flops.totals(N, M, R, P, depth, R, None, crow))
+        print(json.dumps({"sweep": name, "N": N, "M": M, "R": R, "P": P, "depth": depth, "coupling_rows": crow,
+                          "levels": len(flops.levels(N, M, P, depth, R, None, crow)),
+                          "ms_per_solve": ms, "solves_per_s": 1e3 / ms, "gflop": fl / 1e9,
+                          "tflops": fl / (ms * 1e-3) / 1e12, "residual_max": resid}), flush=True)
+        del run
+        torch.cuda.empty_cache()
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -272,6 +360,9 @@ def main():
     if args.copy_calib_mib > 0:
         copy_calibration(torch, args.copy_calib_mib)
         return
+    if args.sweep:
+        sweep(torch, args)
+        return
     from paper_1505_06864_amd import btd, flops
     dev = torch.device("cuda:0")
     N, M, R, gen = WORKLOADS[args.workload]
@@ -280,7 +371,8 @@ def main():
     crow = args.coupling_rows if args.coupling_rows is not None else DEFAULT_COUPLING_ROWS
     (A, B, C, F), host = make_inputs(torch, args.workload, dev)
     seps = btd.balanced_separators(N, P) if args.balanced else None
-    run = Runner(torch, A, B, C, F, P, depth, crow, seps)
+    run = Runner(torch, A, B, C, F, P, depth, crow, seps, args.prec)
+    mixed = args.prec == "f32_refine"
 
     for _ in range(args.warmup):
         run.step()
@@ -300,8 +392,15 @@ def main():
     run.release()
     dom = max(class_ms, key=class_ms.get) if args.roofline_class == "auto" else args.roofline_class
 
-    # timed region: K steps, per-step events on the launch stream, dominant class bracketed
+    # one untimed step with the dominant class bracketed, so the timed
+    # region reuses its events (two event records per launch, no creation)
     btd.profile_enable(dom)
+    run.step()
+    torch.cuda.synchronize()
+    btd.profile_read()
+    run.release()
+
+    # timed region: K steps, per-step events on the launch stream, dominant class bracketed
     evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -336,9 +435,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if not mixed else "f32 products + f64 refinement",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {gen} blocks, N={N}, M={M}, R={R}, FP64",
+        "config": {"workload": f"{args.workload}: {gen} blocks, N={N}, M={M}, R={R}, "
+                               + ("FP64" if not mixed else "FP32 factor products + FP64 refinement to 1e-12"),
                    "N": N, "M": M, "R": R, "P": P, "depth": depth, "coupling_rows": crow,
                    "partition": "balanced (Sec. 4)" if args.balanced else "equal"},
         "tflops": tflops,
@@ -358,11 +458,19 @@ def main():
                      "avg_launch_ms": dom_avg_ms, "launches": dom_n,
                      "gflop_per_launch": dom_flops_per_launch / 1e9},
     }
-    if not args.no_breakdown:
+    # bytes every step must move at least once (read A, B, C, F, write X): the
+    # HBM rate of the whole step, the figure that matters for small blocks
+    out["hbm_gbs_unique"] = flops.unique_bytes(N, M, R) / (ms_step * 1e-3) / 1e9
+    if mixed:
+        out["refinement"] = {"corrections_per_solve": sorted(set(run.iters)), "final_residual_max": max(run.refine_res),
+                             "tolerance": 1e-12}
+    if not args.no_breakdown and not mixed:
         out["breakdown"] = breakdown(torch, run, A, B, C, F, ms_step)
+        # the same K steps with no profiling events at all
+        out["breakdown"]["ms_per_step_unprofiled"] = time_steps(torch, run, args.steps, warmup=0)[0]
     if not args.no_cpu_baseline:
-        rows = args.cpu_sample_rows or (768 if M >= 256 else (1024 if M >= 128 else N))
-        out["cpu_baseline"] = cpu_baseline(host, P, depth, rows, args.workload)
+        rows = args.cpu_sample_rows or (1535 if M >= 256 else (1024 if M >= 128 else N))
+        out["cpu_baseline"] = cpu_baseline(host, P, depth, crow, rows, args.workload)
     print(json.dumps(out), flush=True)
 
 

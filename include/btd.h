@@ -61,8 +61,16 @@ extern "C" {
 #define BTD_ERR_NONFINITE 2  /* a pivot that is NaN or infinite                          */
 #define BTD_ERR_LAUNCH 3     /* a HIP launch or copy failed (returned by the call)       */
 #define BTD_ERR_SCRATCH 4    /* btd_solve_noalloc: the solve needs more than the static scratch */
+#define BTD_ERR_NOT_CONVERGED 5 /* btd_solve_refine: the tolerance was not reached             */
 
 #define BTD_PREC_F64 0
+/* Mixed precision: the block products of the factor sweeps of the top level
+ * (the Schur complements D_i = A_i - B_i E_{i-1} and the spike products)
+ * run on FP32 MFMA with FP32 accumulation; everything is stored in FP64, and
+ * the LU of D_i, the coupling systems, every solve, the residual and the
+ * correction stay FP64.  btd_solve then gives about FP32 accuracy;
+ * btd_solve_refine reaches FP64 accuracy by iterative refinement. */
+#define BTD_PREC_F32_REFINE 1
 
 /* Largest block size the kernels accept (diagonal-block LU panel held in LDS). */
 #define BTD_MAX_M 512
@@ -83,7 +91,7 @@ typedef struct btd_plan_s *btd_plan_t;
  *             R/M)))) capped at floor(P/3), at least 2; levels whose
  *             coupling system has fewer than 3 rows use the Thomas
  *             algorithm).  R here is max_nrhs.
- *   prec      BTD_PREC_F64.
+ *   prec      BTD_PREC_F64 or BTD_PREC_F32_REFINE.
  *   max_nrhs  largest R a later btd_solve may use (>= 1).
  *   seps      NULL for the equal split (subsystem sizes floor((N-P+1)/P),
  *             the first (N-P+1) mod P subsystems one row longer), or a HOST
@@ -159,6 +167,27 @@ int btd_solve(btd_plan_t plan, int32_t nrhs, const double *F, double *X, void *s
 int btd_solve_batch(int32_t count, const btd_plan_t *plans, const int32_t *nrhs,
                     const double *const *F, double *const *X, void *solve_ws, size_t solve_bytes,
                     void *stream);
+
+/*
+ * Iterative refinement (for BTD_PREC_F32_REFINE plans; any plan works):
+ *   X = solve(F); then while max_c ||F - A X||_2 / ||F||_2 > tol and fewer
+ *   than max_iter corrections were made: D = solve(F - A X), X += D,
+ * with the residual F - A X and the correction X += D in FP64 against the
+ * plan's FP64 blocks A, B, C.  BLOCKING: the residual norms are read on the
+ * host after every residual (the call synchronises `stream` each time), so
+ * it cannot be captured in a graph.  work (>= btd_refine_work_bytes, 256-byte
+ * aligned) holds the solve workspace, the residual vector and the norms.
+ * *iters (may be NULL) = corrections made; *resid (may be NULL) = the final
+ * max_c relative residual.  X must not alias F.
+ * Returns 0 when the final residual is <= tol; BTD_ERR_NOT_CONVERGED when
+ * it is not after max_iter corrections (X holds the last iterate);
+ * -1 NULL plan; -2 nrhs out of range; -3/-4 NULL F/X or X == F; -5 NULL or
+ * misaligned work; -6 work too small; -7 tol not positive or max_iter < 0;
+ * BTD_ERR_LAUNCH.
+ */
+size_t btd_refine_work_bytes(btd_plan_t plan, int32_t nrhs);
+int btd_solve_refine(btd_plan_t plan, int32_t nrhs, const double *F, double *X, void *work, size_t work_bytes,
+                     double tol, int32_t max_iter, int32_t *iters, double *resid, void *stream);
 
 /*
  * btd_solve without a workspace argument, for callers that cannot allocate
@@ -308,7 +337,8 @@ int btd_coupling_parts(int32_t P, int32_t M, int32_t R, int32_t coupling_rows);
  * that kernel class (on the process's plans, any stream) is bracketed by a
  * pair of HIP events recorded on the launch's stream.  btd_profile_read
  * waits for the recorded events, returns the summed elapsed milliseconds and
- * the number of launches since the last read, and releases the events.
+ * the number of launches since the last read, and keeps the events for
+ * later launches (a measured pass after the first creates no events).
  * Classes: see BTD_KC_*.  btd_profile_enable(-1) disables.  The record is
  * process-wide (guarded by a lock).  Returns 0, or -1 for an unknown class.
  */

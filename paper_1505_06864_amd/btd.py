@@ -16,13 +16,15 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbtd.so")
 
-BTD_OK, BTD_ERR_SINGULAR, BTD_ERR_NONFINITE, BTD_ERR_LAUNCH, BTD_ERR_SCRATCH = 0, 1, 2, 3, 4
+BTD_OK, BTD_ERR_SINGULAR, BTD_ERR_NONFINITE, BTD_ERR_LAUNCH, BTD_ERR_SCRATCH, BTD_ERR_NOT_CONVERGED = 0, 1, 2, 3, 4, 5
 NOALLOC_SCRATCH_BYTES = 64 << 20
 BTD_PREC_F64 = 0
+BTD_PREC_F32_REFINE = 1
+PRECISIONS = {"f64": BTD_PREC_F64, "f32_refine": BTD_PREC_F32_REFINE}
 BTD_MAX_M = 512
 
 # Every symbol include/btd.h declares.
-EXPORTS = ("btd_workspace_bytes", "btd_factor", "btd_solve", "btd_solve_batch", "btd_solve_noalloc", "btd_solve_local",
+EXPORTS = ("btd_workspace_bytes", "btd_factor", "btd_solve", "btd_solve_batch", "btd_solve_noalloc", "btd_refine_work_bytes", "btd_solve_refine", "btd_solve_local",
            "btd_solve_finish", "btd_get_solve_info", "btd_plan_level_arrays", "btd_residual_work_bytes",
            "btd_residual", "btd_get_info", "btd_plan_separators", "btd_plan_level_parts",
            "btd_default_separators", "btd_balanced_separators", "btd_default_coupling_parts",
@@ -62,6 +64,10 @@ def lib():
         L.btd_solve_batch.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(i32), ctypes.POINTER(vp),
                                       ctypes.POINTER(vp), vp, sz, vp]
         L.btd_solve_noalloc.argtypes = [vp, i32, vp, vp, vp]
+        L.btd_refine_work_bytes.argtypes = [vp, i32]
+        L.btd_refine_work_bytes.restype = sz
+        L.btd_solve_refine.argtypes = [vp, i32, vp, vp, vp, sz, ctypes.c_double, i32, ctypes.POINTER(i32),
+                                       ctypes.POINTER(ctypes.c_double), vp]
         L.btd_solve_local.argtypes = [vp, i32, vp, vp, vp, vp]
         L.btd_solve_finish.argtypes = [vp, i32, vp, vp, vp]
         L.btd_get_solve_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
@@ -134,8 +140,8 @@ def _aligned_buffer(nbytes, device, stream=None):
     return buf, ptr
 
 
-def make_desc(N, M, P=1, depth=0, max_nrhs=1, seps=None, coupling_rows=0):
-    d = Desc(N, M, P, depth, BTD_PREC_F64, max_nrhs, None, coupling_rows)
+def make_desc(N, M, P=1, depth=0, max_nrhs=1, seps=None, coupling_rows=0, prec="f64"):
+    d = Desc(N, M, P, depth, PRECISIONS[prec], max_nrhs, None, coupling_rows)
     keep = None
     if seps is not None:
         keep = (ctypes.c_int32 * max(len(seps), 1))(*[int(q) for q in seps])
@@ -191,16 +197,16 @@ def coupling_parts(P, M, R, coupling_rows=0):
 class Plan:
     """A factored system (btd_factor).  Keeps A, B, C and the factor workspace alive."""
 
-    def __init__(self, A, B, C, P=1, depth=0, max_nrhs=1, seps=None, stream=None, coupling_rows=0):
+    def __init__(self, A, B, C, P=1, depth=0, max_nrhs=1, seps=None, stream=None, coupling_rows=0, prec="f64"):
         N, M = A.shape[0], A.shape[1]
         for t, n in ((A, "A"), (B, "B"), (C, "C")):
             _check(t, n, (N, M, M))
-        self.N, self.M, self.P, self.depth, self.max_nrhs = N, M, P, depth, max_nrhs
+        self.N, self.M, self.P, self.depth, self.max_nrhs, self.prec = N, M, P, depth, max_nrhs, prec
         self.device = A.device
         self.A, self.B, self.C = A, B, C
         fbytes, self.solve_bytes = workspace_bytes(N, M, P, depth, max_nrhs, seps, coupling_rows)
         self._ws, ptr = _aligned_buffer(fbytes, A.device, stream)
-        d, _keep = make_desc(N, M, P, depth, max_nrhs, seps, coupling_rows)
+        d, _keep = make_desc(N, M, P, depth, max_nrhs, seps, coupling_rows, prec)
         h = ctypes.c_void_p()
         rc = lib().btd_factor(ctypes.byref(d), A.data_ptr(), B.data_ptr(), C.data_ptr(), ptr, fbytes,
                               _stream_handle(stream, A.device), ctypes.byref(h))
@@ -227,6 +233,25 @@ class Plan:
             raise BtdError(rc, "btd_solve")
         self._last_solve_ws = buf  # lives until the next solve on this plan (stream-ordered reuse)
         return X
+
+    def solve_refine(self, F, X=None, tol=1e-12, max_iter=5, stream=None):
+        """Iteratively refined solve (btd_solve_refine; blocking).  Returns
+        (X, corrections made, final max relative residual); raises
+        BtdError(BTD_ERR_NOT_CONVERGED) when tol is not reached."""
+        R = F.shape[2]
+        _check(F, "F", (self.N, self.M, R))
+        if X is None:
+            X = _empty_on(stream, F.shape, dtype=F.dtype, device=F.device)
+        _check(X, "X", (self.N, self.M, R))
+        nbytes = lib().btd_refine_work_bytes(self._h, R)
+        buf, ptr = _aligned_buffer(nbytes, F.device, stream)
+        it, res = ctypes.c_int32(), ctypes.c_double()
+        rc = lib().btd_solve_refine(self._h, R, F.data_ptr(), X.data_ptr(), ptr, nbytes, ctypes.c_double(tol),
+                                    max_iter, ctypes.byref(it), ctypes.byref(res), _stream_handle(stream, F.device))
+        del buf   # the call synchronised its stream
+        if rc != BTD_OK:
+            raise BtdError(rc, f"btd_solve_refine (residual {res.value:.3e} after {it.value} corrections)")
+        return X, it.value, res.value
 
     def solve_local(self, F, X=None, Fhat=None, stream=None):
         """The per-subsystem half of a solve (btd_solve_local): z into the
@@ -345,8 +370,9 @@ class Plan:
             pass
 
 
-def factor(A, B, C, P=1, depth=0, max_nrhs=1, seps=None, stream=None, coupling_rows=0):
-    return Plan(A, B, C, P=P, depth=depth, max_nrhs=max_nrhs, seps=seps, stream=stream, coupling_rows=coupling_rows)
+def factor(A, B, C, P=1, depth=0, max_nrhs=1, seps=None, stream=None, coupling_rows=0, prec="f64"):
+    return Plan(A, B, C, P=P, depth=depth, max_nrhs=max_nrhs, seps=seps, stream=stream, coupling_rows=coupling_rows,
+                prec=prec)
 
 
 def solve_batch(plans, Fs, Xs=None, stream=None, lanes=1):

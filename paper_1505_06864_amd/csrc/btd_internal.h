@@ -38,6 +38,7 @@ struct KArgs {
     double* Fc;                // [P-1][M][R] coupling right-hand side / solution h
     unsigned long long* status;
     int c0, nc;                // chunks c0 .. c0+nc-1 handled by a chunk-batched launch
+    int lowp;                  // 1: products of the level-0 factor sweeps in FP32 (BTD_PREC_F32_REFINE)
 };
 
 struct IntChunk {
@@ -68,8 +69,12 @@ hipError_t launch_write_ints(int* dst, const int* host_vals, int count, hipStrea
 // Partial sums per column of the residual kernels (their work array holds
 // 2 * residual_parts * R doubles).
 size_t residual_parts(int N, int M, int R);
+// rout (optional, [N][M][R]): also write the residual vector F - A X.
 hipError_t launch_residual(int N, int M, int R, const double* A, const double* B, const double* C,
-                           const double* X, const double* F, double* out, double* work, hipStream_t s);
+                           const double* X, const double* F, double* out, double* work, hipStream_t s,
+                           double* rout = nullptr);
+// X += D over n doubles.
+hipError_t launch_add(double* X, const double* D, size_t n, hipStream_t s);
 size_t getrf_lds_bytes(int M);
 hipError_t configure_kernels();
 

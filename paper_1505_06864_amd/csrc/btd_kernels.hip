@@ -24,7 +24,15 @@
 
 #include "btd_internal.h"
 
+// Output layout of v_mfma_f32_16x16x4f32: 1 when register v of lane l holds
+// tile row 4 (l >> 4) + v, 0 when it holds row (l >> 4) + 4 v like the FP64
+// instruction.
+#ifndef MFMA_F32_ROWS_BY_LANE_GROUP
+#define MFMA_F32_ROWS_BY_LANE_GROUP 1
+#endif
+
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
 
 namespace btd {
 
@@ -35,6 +43,20 @@ __device__ __forceinline__ int chunk_last(const Level& L, int k) { return L.sep[
 
 __device__ __forceinline__ v4d mfma4(double a, double b, v4d c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+// FP32 products with FP32 accumulation (the reduced-precision factor).
+__device__ __forceinline__ v4f mfma4(float a, float b, v4f c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Accumulator of a 16x16 MFMA tile for a product type, and the tile row that
+// register v of lane l holds (its column is l & 15).
+template <class CT> struct Acc4;
+template <> struct Acc4<double> { typedef v4d type; };
+template <> struct Acc4<float> { typedef v4f type; };
+template <class CT>
+__device__ __forceinline__ int mfma_row(int lane, int v) {
+    return MFMA_F32_ROWS_BY_LANE_GROUP && sizeof(CT) == 4 ? 4 * (lane >> 4) + v : (lane >> 4) + 4 * v;
 }
 
 
@@ -314,28 +336,36 @@ __device__ __forceinline__ void load_tiles(const double* __restrict__ A, int lda
     }
 }
 
-__device__ __forceinline__ void store_tiles(double* As, double* Bs, const double ra[4], const double rb[4]) {
+// The tiles go to LDS in the product type CT (FP64 values rounded to FP32
+// for the reduced-precision factor).
+template <class CT>
+__device__ __forceinline__ void store_tiles(CT* As, CT* Bs, const double ra[4], const double rb[4]) {
     const int tid = threadIdx.x;
     {
         const int rr = tid >> 2, kq = (tid & 3) * 4;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) As[(kq + q) * (TB + AP) + rr] = ra[q];
+        for (int q = 0; q < 4; ++q) As[(kq + q) * (TB + AP) + rr] = (CT)ra[q];
     }
     {
         const int kk = tid >> 4, cq = (tid & 15) * 4;
-        *(double4*)(Bs + kk * (TB + BP) + cq) = make_double4(rb[0], rb[1], rb[2], rb[3]);
+        if constexpr (sizeof(CT) == 8) {
+            *(double4*)(Bs + kk * (TB + BP) + cq) = make_double4(rb[0], rb[1], rb[2], rb[3]);
+        } else {
+            *(float4*)(Bs + kk * (TB + BP) + cq) = make_float4((float)rb[0], (float)rb[1], (float)rb[2], (float)rb[3]);
+        }
     }
 }
 
-__device__ __forceinline__ void tile_mma(const double* as, const double* bs, int lane, int wr, int wc,
-                                         v4d acc[2][2]) {
+template <class CT>
+__device__ __forceinline__ void tile_mma(const CT* as, const CT* bs, int lane, int wr, int wc,
+                                         typename Acc4<CT>::type acc[2][2]) {
 #pragma unroll
     for (int kk = 0; kk < KB / 4; ++kk) {
         const int krow = kk * 4 + (lane >> 4);
-        double a0 = as[krow * (TB + AP) + wr + (lane & 15)];
-        double a1 = as[krow * (TB + AP) + wr + 16 + (lane & 15)];
-        double b0 = bs[krow * (TB + BP) + wc + (lane & 15)];
-        double b1 = bs[krow * (TB + BP) + wc + 16 + (lane & 15)];
+        CT a0 = as[krow * (TB + AP) + wr + (lane & 15)];
+        CT a1 = as[krow * (TB + AP) + wr + 16 + (lane & 15)];
+        CT b0 = bs[krow * (TB + BP) + wc + (lane & 15)];
+        CT b1 = bs[krow * (TB + BP) + wc + 16 + (lane & 15)];
         acc[0][0] = mfma4(a0, b0, acc[0][0]);
         acc[0][1] = mfma4(a0, b1, acc[0][1]);
         acc[1][0] = mfma4(a1, b0, acc[1][0]);
@@ -352,9 +382,10 @@ __device__ __forceinline__ void tile_mma(const double* as, const double* bs, int
 // two steps load the final K step again, unused), which keeps the loop free
 // of branches, so the loads of step s+2 stay in flight while step s+1 is
 // stored.
-template <bool FULL>
+template <bool FULL, class CT>
 __device__ void tile_accumulate_k(const double* __restrict__ A, int lda, const double* __restrict__ Bm, int ldb,
-                                  int K, int row0, int col0, int m, int n, v4d acc[2][2], double* As, double* Bs) {
+                                  int K, int row0, int col0, int m, int n, typename Acc4<CT>::type acc[2][2], CT* As,
+                                  CT* Bs) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
     double ra0[4], rb0[4], ra1[4], rb1[4];
@@ -392,21 +423,25 @@ __device__ void tile_accumulate_k(const double* __restrict__ A, int lda, const d
     }
 }
 
+template <class CT>
 __device__ void tile_accumulate(const double* __restrict__ A, int lda, const double* __restrict__ Bm, int ldb,
-                                int K, int row0, int col0, int m, int n, v4d acc[2][2], double* As, double* Bs) {
+                                int K, int row0, int col0, int m, int n, typename Acc4<CT>::type acc[2][2], CT* As,
+                                CT* Bs) {
     if (K <= 0) return;
     const bool full = row0 + TB <= m && col0 + TB <= n && K % (2 * KB) == 0 && (lda & 3) == 0 &&
                       (ldb & 3) == 0 && ((uintptr_t)A & 31) == 0 && ((uintptr_t)Bm & 31) == 0;
-    if (full) tile_accumulate_k<true>(A, lda, Bm, ldb, K, row0, col0, m, n, acc, As, Bs);
-    else tile_accumulate_k<false>(A, lda, Bm, ldb, K, row0, col0, m, n, acc, As, Bs);
+    if (full) tile_accumulate_k<true, CT>(A, lda, Bm, ldb, K, row0, col0, m, n, acc, As, Bs);
+    else tile_accumulate_k<false, CT>(A, lda, Bm, ldb, K, row0, col0, m, n, acc, As, Bs);
 }
 
 // At most 128 VGPRs (four waves per SIMD, as many as the LDS admits) except
 // for the coupling right-hand sides, whose job set-up needs more.
-template <int MODE, int NPARTS>
+// CT: product type (double; float = FP32 products with FP32 accumulation,
+// added to the FP64 Cin in FP64).
+template <int MODE, int NPARTS, class CT = double>
 __global__ __launch_bounds__(256, MODE == GM_COUPLE_RHS ? 3 : 4) void k_gemm(const KArgs ka, int tiles_m, int tiles_n) {
-    __shared__ double As[2 * ASZ];
-    __shared__ double Bs[2 * BSZ];
+    __shared__ CT As[2 * ASZ];
+    __shared__ CT Bs[2 * BSZ];
     const int per_item = tiles_m * tiles_n * NPARTS;
     const int lid = xcd_logical_id(blockIdx.x, gridDim.x);
     const int b = lid / per_item;
@@ -418,13 +453,13 @@ __global__ __launch_bounds__(256, MODE == GM_COUPLE_RHS ? 3 : 4) void k_gemm(con
     if (!make_job<MODE>(ka, b, part, j)) return;
     const int row0 = tm * TB, col0 = tn * TB;
     if (row0 >= j.m || col0 >= j.n) return;
-    v4d acc[2][2];
+    typename Acc4<CT>::type acc[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int c = 0; c < 2; ++c) acc[a][c] = (v4d){0.0, 0.0, 0.0, 0.0};
-    tile_accumulate(j.A1, j.lda1, j.B1, j.ldb1, j.k1, row0, col0, j.m, j.n, acc, As, Bs);
-    tile_accumulate(j.A2, j.lda2, j.B2, j.ldb2, j.k2, row0, col0, j.m, j.n, acc, As, Bs);
+        for (int c = 0; c < 2; ++c) acc[a][c] = (typename Acc4<CT>::type){0, 0, 0, 0};
+    tile_accumulate<CT>(j.A1, j.lda1, j.B1, j.ldb1, j.k1, row0, col0, j.m, j.n, acc, As, Bs);
+    tile_accumulate<CT>(j.A2, j.lda2, j.B2, j.ldb2, j.k2, row0, col0, j.m, j.n, acc, As, Bs);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int wr = row0 + (w >> 1) * 32, wc = col0 + (w & 1) * 32;
 #pragma unroll
@@ -434,10 +469,10 @@ __global__ __launch_bounds__(256, MODE == GM_COUPLE_RHS ? 3 : 4) void k_gemm(con
             const int col = wc + 16 * c + (lane & 15);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int row = wr + 16 * a + (lane >> 4) + 4 * v;
+                const int row = wr + 16 * a + mfma_row<CT>(lane, v);
                 if (row < j.m && col < j.n) {
                     double base = j.Cin ? j.Cin[(size_t)row * j.ldc + col] : 0.0;
-                    j.Out[(size_t)row * j.ldo + col] = base + j.alpha * acc[a][c][v];
+                    j.Out[(size_t)row * j.ldo + col] = base + j.alpha * (double)acc[a][c][v];
                     if (j.CopyOut) j.CopyOut[(size_t)row * j.ldco + col] = j.CopyIn[(size_t)row * j.ldci + col];
                 }
             }
@@ -1643,8 +1678,8 @@ __host__ __device__ constexpr int trsm_pair(int p, bool fwd, bool want_src) {
 }
 
 // x_bp -= T_{bp,b} x_b (the operand already negated)
-template <int NBLK, int NT16, int B, int BP>
-__device__ __forceinline__ void trsmw_update(v4d (&x)[NBLK][2][NT16], const double (&o)[2][8]) {
+template <int NBLK, int NT16, int B, int BP, class CT, class V4>
+__device__ __forceinline__ void trsmw_update(V4 (&x)[NBLK][2][NT16], const CT (&o)[2][8]) {
 #pragma unroll
     for (int kk = 0; kk < 8; ++kk)
 #pragma unroll
@@ -1737,43 +1772,58 @@ __device__ __forceinline__ double4 tseq_load(int e, const double* __restrict__ l
 }
 
 // Store a piece of sequence element e in operand order (negated for pairs,
-// zeros outside the matrix): block row r is row tile tr = (r >> 2) & 1,
-// tile row i16 = (r >> 3) | ((r & 3) << 2); column c = 8 g + kk.
-template <int NBLK, int PC>
-__device__ __forceinline__ void tseq_stage(int e, double* slot, int tid, double4 v, int valid) {
+// zeros outside the matrix), rounded to the product type CT: block row r
+// (held in lane group g = r >> 3, register v = r & 3 of row tile
+// tr = (r >> 2) & 1) is the MFMA output row i16 that register v of lane group
+// g holds; column c = 8 g + kk.
+template <int NBLK, int PC, class CT = double>
+__device__ __forceinline__ void tseq_stage(int e, CT* slot, int tid, double4 v, int valid) {
     constexpr int PR = DB / PC;
     const int kind = tseq_kind<NBLK>(e);
     const double sg = (kind == 0 || kind == 2) ? -1.0 : 1.0;
     const double x0 = (valid & 1) ? sg * v.x : 0.0, x1 = (valid & 2) ? sg * v.y : 0.0;
     const double x2 = (valid & 4) ? sg * v.z : 0.0, x3 = (valid & 8) ? sg * v.w : 0.0;
     const int r = tid / PR, c4 = (tid % PR) * PC;
-    const int tr = (r >> 2) & 1, i16 = (r >> 3) | ((r & 3) << 2);
+    const int tr = (r >> 2) & 1, i16 = mfma_row<CT>((r >> 3) << 4, r & 3);
     const int g = c4 >> 3, kk = c4 & 7;
-    double* d = slot + (tr * 64 + g * 16 + i16) * TS_LANE + kk;
-    *(double2*)d = make_double2(x0, x1);
-    if (PC == 4) *(double2*)(d + 2) = make_double2(x2, x3);
+    CT* d = slot + (tr * 64 + g * 16 + i16) * TS_LANE + kk;
+    if constexpr (sizeof(CT) == 8) {
+        *(double2*)d = make_double2(x0, x1);
+        if (PC == 4) *(double2*)(d + 2) = make_double2(x2, x3);
+    } else {
+        *(float2*)d = make_float2((float)x0, (float)x1);
+        if (PC == 4) *(float2*)(d + 2) = make_float2((float)x2, (float)x3);
+    }
 }
 
-template <int NBLK, int NT16, int E>
-__device__ __forceinline__ void tseq_apply(v4d (&x)[NBLK][2][NT16], const double* slot, int lane) {
+template <int NBLK, int NT16, int E, class CT = double>
+__device__ __forceinline__ void tseq_apply(typename Acc4<CT>::type (&x)[NBLK][2][NT16], const CT* slot, int lane) {
+    typedef typename Acc4<CT>::type V4;
     constexpr int kind = tseq_kind<NBLK>(E), B = tseq_b<NBLK>(E), BP = tseq_bp<NBLK>(E);
-    double o[2][8];
+    CT o[2][8];
 #pragma unroll
     for (int tr = 0; tr < 2; ++tr) {
-        const double* src = slot + (tr * 64 + lane) * TS_LANE;
-        const double2 a0 = *(const double2*)src, a1 = *(const double2*)(src + 2);
-        const double2 a2 = *(const double2*)(src + 4), a3 = *(const double2*)(src + 6);
-        o[tr][0] = a0.x; o[tr][1] = a0.y; o[tr][2] = a1.x; o[tr][3] = a1.y;
-        o[tr][4] = a2.x; o[tr][5] = a2.y; o[tr][6] = a3.x; o[tr][7] = a3.y;
+        const CT* src = slot + (tr * 64 + lane) * TS_LANE;
+        if constexpr (sizeof(CT) == 8) {
+            const double2 a0 = *(const double2*)src, a1 = *(const double2*)(src + 2);
+            const double2 a2 = *(const double2*)(src + 4), a3 = *(const double2*)(src + 6);
+            o[tr][0] = a0.x; o[tr][1] = a0.y; o[tr][2] = a1.x; o[tr][3] = a1.y;
+            o[tr][4] = a2.x; o[tr][5] = a2.y; o[tr][6] = a3.x; o[tr][7] = a3.y;
+        } else {
+            const float2 a0 = *(const float2*)src, a1 = *(const float2*)(src + 2);
+            const float2 a2 = *(const float2*)(src + 4), a3 = *(const float2*)(src + 6);
+            o[tr][0] = a0.x; o[tr][1] = a0.y; o[tr][2] = a1.x; o[tr][3] = a1.y;
+            o[tr][4] = a2.x; o[tr][5] = a2.y; o[tr][6] = a3.x; o[tr][7] = a3.y;
+        }
     }
     if constexpr (kind == 0 || kind == 2) {
         trsmw_update<NBLK, NT16, B, BP>(x, o);
     } else {
-        v4d nw[2][NT16];
+        V4 nw[2][NT16];
 #pragma unroll
         for (int tr = 0; tr < 2; ++tr)
 #pragma unroll
-            for (int nt = 0; nt < NT16; ++nt) nw[tr][nt] = (v4d){0.0, 0.0, 0.0, 0.0};
+            for (int nt = 0; nt < NT16; ++nt) nw[tr][nt] = (V4){0, 0, 0, 0};
 #pragma unroll
         for (int kk = 0; kk < 8; ++kk)
 #pragma unroll
@@ -1790,27 +1840,30 @@ __device__ __forceinline__ void tseq_apply(v4d (&x)[NBLK][2][NT16], const double
 // Sequence element E: stage E+1 (loaded two elements ago), start loading
 // E+3, apply E, barrier.  p0/p1 (validity m0/m1) hold the pieces of E+1 and
 // E+2 on entry.
-template <int NBLK, int NT16, int PC, int E>
-__device__ __forceinline__ void tseq_run(v4d (&x)[NBLK][2][NT16], double* ring, const double* __restrict__ lu,
-                                         const double* __restrict__ di, int M, int nblk, int tid, int lane,
-                                         double4& p0, int m0, double4& p1, int m1) {
+template <int NBLK, int NT16, int PC, int E, class CT = double>
+__device__ __forceinline__ void tseq_run(typename Acc4<CT>::type (&x)[NBLK][2][NT16], CT* ring,
+                                         const double* __restrict__ lu, const double* __restrict__ di, int M, int nblk,
+                                         int tid, int lane, double4& p0, int m0, double4& p1, int m1) {
     constexpr int NS = trsm_nseq<NBLK>();
     if constexpr (E < NS) {
-        if constexpr (E + 1 < NS) tseq_stage<NBLK, PC>(E + 1, ring + ((E + 1) % TS_RING) * TS_BLOCK, tid, p0, m0);
+        if constexpr (E + 1 < NS) tseq_stage<NBLK, PC, CT>(E + 1, ring + ((E + 1) % TS_RING) * TS_BLOCK, tid, p0, m0);
         double4 p2 = {0.0, 0.0, 0.0, 0.0};
         int m2 = 0;
         if constexpr (E + 3 < NS) p2 = tseq_load<NBLK, PC>(E + 3, lu, di, M, nblk, tid, m2);
-        tseq_apply<NBLK, NT16, E>(x, ring + (E % TS_RING) * TS_BLOCK, lane);
+        tseq_apply<NBLK, NT16, E, CT>(x, ring + (E % TS_RING) * TS_BLOCK, lane);
         __syncthreads();
-        tseq_run<NBLK, NT16, PC, E + 1>(x, ring, lu, di, M, nblk, tid, lane, p1, m1, p2, m2);
+        tseq_run<NBLK, NT16, PC, E + 1, CT>(x, ring, lu, di, M, nblk, tid, lane, p1, m1, p2, m2);
     }
 }
 
 // RHS: the right-hand-side sweep's X_i (R columns, in place) instead of
-// W_i = [C_i | -B_i Y_{i-1}].
-template <int NBLK, int NT16, int WPB, bool RHS = false>
+// W_i = [C_i | -B_i Y_{i-1}].  CT: product type (float: FP32 MFMA with FP32
+// accumulation on the FP64 factors and right-hand side, for the
+// reduced-precision factor; results stored in FP64).
+template <int NBLK, int NT16, int WPB, bool RHS = false, class CT = double>
 __global__ __launch_bounds__(64 * WPB) void k_getrs_s(const KArgs ka, int nslab, int wpc) {
-    __shared__ double ring[TS_RING * TS_BLOCK];
+    typedef typename Acc4<CT>::type V4;
+    __shared__ CT ring[TS_RING * TS_BLOCK];
     const Level& L = ka.L;
     const int M = L.M;
     const int lid = xcd_logical_id(blockIdx.x, gridDim.x);
@@ -1845,7 +1898,7 @@ __global__ __launch_bounds__(64 * WPB) void k_getrs_s(const KArgs ka, int nslab,
     // (the forward product does not copy it for this kernel); the solution
     // goes to W_i.
     const double* Ci = RHS ? X : L.C + (size_t)i * M * M;
-    v4d x[NBLK][2][NT16];
+    V4 x[NBLK][2][NT16];
 #pragma unroll
     for (int b = 0; b < NBLK; ++b)
 #pragma unroll
@@ -1862,7 +1915,7 @@ __global__ __launch_bounds__(64 * WPB) void k_getrs_s(const KArgs ka, int nslab,
                 const int lds = fromC ? M : ld;
                 const int cs = cv ? col : 0;
 #pragma unroll
-                for (int v = 0; v < 4; ++v) x[b][tr][nt][v] = src[(uint32_t)(prw[v] * lds + cs)];
+                for (int v = 0; v < 4; ++v) x[b][tr][nt][v] = (CT)src[(uint32_t)(prw[v] * lds + cs)];
             }
         }
 #pragma unroll
@@ -1876,12 +1929,12 @@ __global__ __launch_bounds__(64 * WPB) void k_getrs_s(const KArgs ka, int nslab,
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int row = b * DB + 8 * g + 4 * tr + v;
-                    x[b][tr][nt][v] = (cv && row < M) ? x[b][tr][nt][v] : 0.0;
+                    x[b][tr][nt][v] = (cv && row < M) ? x[b][tr][nt][v] : (CT)0;
                 }
             }
-    tseq_stage<NBLK, PC>(0, ring, tid, p0, m0);
+    tseq_stage<NBLK, PC, CT>(0, ring, tid, p0, m0);
     __syncthreads();
-    tseq_run<NBLK, NT16, PC, 0>(x, ring, lu, di, M, nblk, tid, lane, p1, m1, p2, m2);
+    tseq_run<NBLK, NT16, PC, 0, CT>(x, ring, lu, di, M, nblk, tid, lane, p1, m1, p2, m2);
 #pragma unroll
     for (int b = 0; b < NBLK; ++b)
 #pragma unroll
@@ -1893,7 +1946,7 @@ __global__ __launch_bounds__(64 * WPB) void k_getrs_s(const KArgs ka, int nslab,
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int row = b * DB + 8 * g + 4 * tr + v;
-                    if (cv && row < M) X[(uint32_t)(row * ld + col)] = x[b][tr][nt][v];
+                    if (cv && row < M) X[(uint32_t)(row * ld + col)] = (double)x[b][tr][nt][v];
                 }
             }
 }
@@ -2108,6 +2161,12 @@ __global__ __launch_bounds__(256) void k_check_finite(const double* __restrict__
     }
 }
 
+// X += D over n doubles (the correction of iterative refinement, FP64).
+__global__ __launch_bounds__(256) void k_add(double* __restrict__ X, const double* __restrict__ D, size_t n) {
+    const size_t stride = (size_t)gridDim.x * 256;
+    for (size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x; idx < n; idx += stride) X[idx] += D[idx];
+}
+
 // sep table of a level: written from kernel arguments (no host-to-device copy)
 __global__ void k_write_ints(int* dst, int count, IntChunk vals) {
     const int t = threadIdx.x;
@@ -2194,10 +2253,11 @@ __global__ __launch_bounds__(256) void k_recover_v(const KArgs ka) {
 // three X columns held in registers, four rows in flight, and a DPP sum per
 // row.  The workgroup writes its partial sums (no atomics: the reduction
 // order is fixed); a second kernel sums them.
+// rout (optional): the residual vector r itself, [N][M][R].
 __global__ __launch_bounds__(256) void k_residual_rows(int N, int M, int R, const double* __restrict__ A,
                                                       const double* __restrict__ B, const double* __restrict__ C,
                                                       const double* __restrict__ X, const double* __restrict__ F,
-                                                      double* __restrict__ part) {
+                                                      double* __restrict__ part, double* __restrict__ rout) {
     const int i = blockIdx.x, c = blockIdx.y;
     const size_t MM = (size_t)M * M, MR = (size_t)M * R;
     __shared__ double sr[4], sf[4];
@@ -2250,6 +2310,7 @@ __global__ __launch_bounds__(256) void k_residual_rows(int N, int M, int R, cons
                 const double tot = wave_sum(s[u]);
                 const double f = F[i * MR + (size_t)(r0 + u) * R + c];
                 const double rv = f - tot;
+                if (rout && lane == 0) rout[i * MR + (size_t)(r0 + u) * R + c] = rv;
                 accr += rv * rv;
                 accf += f * f;
             }
@@ -2265,6 +2326,7 @@ __global__ __launch_bounds__(256) void k_residual_rows(int N, int M, int R, cons
             const double tot = wave_sum(acc);
             const double f = F[i * MR + (size_t)row * R + c];
             const double rv = f - tot;
+            if (rout && lane == 0) rout[i * MR + (size_t)row * R + c] = rv;
             accr += rv * rv;
             accf += f * f;
         }
@@ -2287,7 +2349,7 @@ constexpr int RES_TILE_MIN_R = 2;   // one column: the row kernel (HBM-bound)
 __global__ __launch_bounds__(256) void k_residual_tiles(int N, int M, int R, const double* __restrict__ A,
                                                        const double* __restrict__ B, const double* __restrict__ C,
                                                        const double* __restrict__ X, const double* __restrict__ F,
-                                                       double* __restrict__ part) {
+                                                       double* __restrict__ part, double* __restrict__ rout) {
     __shared__ double As[2 * ASZ];
     __shared__ double Bs[2 * BSZ];
     __shared__ double red[2][4][2][64];   // [r / F][wave][column tile][lane]
@@ -2320,6 +2382,7 @@ __global__ __launch_bounds__(256) void k_residual_tiles(int N, int M, int R, con
                 if (row < M && col < R) {
                     const double f = F[i * MR + (size_t)row * R + col];
                     const double rv = f - acc[a][c][v];
+                    if (rout) rout[i * MR + (size_t)row * R + col] = rv;
                     sr = fma(rv, rv, sr);
                     sf = fma(f, f, sf);
                 }
@@ -2364,16 +2427,24 @@ __global__ __launch_bounds__(256) void k_residual_final(int N, int R, const doub
 
 static inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 
-template <int MODE, int NPARTS>
+template <int MODE, int NPARTS, class CT = double>
 static hipError_t launch_gemm(const KArgs& ka, int batch, int m, int n, hipStream_t s) {
     const int tm = cdiv(m, TB), tn = cdiv(n, TB);
     dim3 grid(tm * tn * NPARTS * batch);
-    hipLaunchKernelGGL((k_gemm<MODE, NPARTS>), grid, dim3(256), 0, s, ka, tm, tn);
+    hipLaunchKernelGGL((k_gemm<MODE, NPARTS, CT>), grid, dim3(256), 0, s, ka, tm, tn);
     return hipGetLastError();
 }
 
-hipError_t launch_fwd_gemm(const KArgs& ka, hipStream_t s) { return launch_gemm<GM_FWD, 2>(ka, ka.nc, ka.L.M, ka.L.M, s); }
-hipError_t launch_bwd_gemm(const KArgs& ka, hipStream_t s) { return launch_gemm<GM_BWD, 2>(ka, ka.nc, ka.L.M, ka.L.M, s); }
+// ka.lowp: the Schur-complement and spike products of the factor in FP32
+// (FP32 MFMA, FP32 accumulation) instead of FP64.
+hipError_t launch_fwd_gemm(const KArgs& ka, hipStream_t s) {
+    return ka.lowp ? launch_gemm<GM_FWD, 2, float>(ka, ka.nc, ka.L.M, ka.L.M, s)
+                   : launch_gemm<GM_FWD, 2>(ka, ka.nc, ka.L.M, ka.L.M, s);
+}
+hipError_t launch_bwd_gemm(const KArgs& ka, hipStream_t s) {
+    return ka.lowp ? launch_gemm<GM_BWD, 2, float>(ka, ka.nc, ka.L.M, ka.L.M, s)
+                   : launch_gemm<GM_BWD, 2>(ka, ka.nc, ka.L.M, ka.L.M, s);
+}
 hipError_t launch_couple(const KArgs& ka, hipStream_t s) { return launch_gemm<GM_COUPLE, 3>(ka, ka.L.P - 1, ka.L.M, ka.L.M, s); }
 hipError_t launch_couple_rhs(const KArgs& ka, hipStream_t s) { return launch_gemm<GM_COUPLE_RHS, 1>(ka, ka.L.P - 1, ka.L.M, ka.R, s); }
 hipError_t launch_recover(const KArgs& ka, hipStream_t s) {
@@ -2413,7 +2484,11 @@ static int slab_width(int M) { return M <= 256 ? 32 : 16; }
 template <int NBLK, int NT16, int WPB = 4, bool RHS = false>
 static void launch_getrs_s(const KArgs& ka, hipStream_t s) {
     const int nslab = cdiv(RHS ? ka.R : 2 * ka.L.M, 16 * NT16), wpc = cdiv(nslab, WPB);
-    hipLaunchKernelGGL((k_getrs_s<NBLK, NT16, WPB, RHS>), dim3(wpc * ka.nc), dim3(64 * WPB), 0, s, ka, nslab, wpc);
+    if (!RHS && ka.lowp)
+        hipLaunchKernelGGL((k_getrs_s<NBLK, NT16, WPB, false, float>), dim3(wpc * ka.nc), dim3(64 * WPB), 0, s, ka,
+                           nslab, wpc);
+    else
+        hipLaunchKernelGGL((k_getrs_s<NBLK, NT16, WPB, RHS>), dim3(wpc * ka.nc), dim3(64 * WPB), 0, s, ka, nslab, wpc);
 }
 
 // M <= 256: slabs of 32 columns (64 for M <= 64; 16 above M = 128, so that
@@ -2495,6 +2570,12 @@ hipError_t launch_check_finite(const double* F, int N, int M, int R, unsigned lo
     return hipGetLastError();
 }
 
+hipError_t launch_add(double* X, const double* D, size_t n, hipStream_t s) {
+    const int blocks = (int)std::min<size_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_add, dim3(blocks), dim3(256), 0, s, X, D, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_write_ints(int* dst, const int* host_vals, int count, hipStream_t s) {
     for (int off = 0; off < count; off += IntChunk::CAP) {
         IntChunk c;
@@ -2512,12 +2593,12 @@ size_t residual_parts(int N, int M, int R) {
 }
 
 hipError_t launch_residual(int N, int M, int R, const double* A, const double* B, const double* C, const double* X,
-                           const double* F, double* out, double* work, hipStream_t s) {
+                           const double* F, double* out, double* work, hipStream_t s, double* rout) {
     if (R >= RES_TILE_MIN_R) {
         const int ntm = cdiv(M, TB), ntn = cdiv(R, TB);
-        hipLaunchKernelGGL(k_residual_tiles, dim3(N * ntm * ntn), dim3(256), 0, s, N, M, R, A, B, C, X, F, work);
+        hipLaunchKernelGGL(k_residual_tiles, dim3(N * ntm * ntn), dim3(256), 0, s, N, M, R, A, B, C, X, F, work, rout);
     } else {
-        hipLaunchKernelGGL(k_residual_rows, dim3(N, R), dim3(256), 0, s, N, M, R, A, B, C, X, F, work);
+        hipLaunchKernelGGL(k_residual_rows, dim3(N, R), dim3(256), 0, s, N, M, R, A, B, C, X, F, work, rout);
     }
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;

@@ -67,7 +67,7 @@ bool valid_desc(const btd_desc_t* d) {
     if (!d) return false;
     if (d->N < 1 || d->M < 1 || d->M > BTD_MAX_M || d->P < 1 || d->depth < 0 || d->max_nrhs < 1) return false;
     if (d->coupling_rows < 0) return false;
-    if (d->prec != BTD_PREC_F64) return false;
+    if (d->prec != BTD_PREC_F64 && d->prec != BTD_PREC_F32_REFINE) return false;
     if (d->P > 1 && 2 * (int64_t)d->P - 1 > d->N) return false;
     if (d->N > (1 << 24) - 1) return false;
     if (d->seps && d->P > 1) {
@@ -210,19 +210,35 @@ int chunk_groups(int P) {
 }
 
 // Event pairs around the launches of one kernel class (measurement only);
-// the class is read without the lock on every launch, the event list is
-// guarded.
+// the class is read without the lock on every launch, the event lists are
+// guarded.  Pairs released by btd_profile_read go to a free list and are
+// recorded again later, so after a first measured pass a launch costs two
+// event records and no event creation.
 struct Profiler {
     std::atomic<int> cls{-1};
     std::mutex mu;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev, spare;
 } g_prof;
+
+bool profile_pair(hipEvent_t& a, hipEvent_t& b) {
+    {
+        std::lock_guard<std::mutex> lock(g_prof.mu);
+        if (!g_prof.spare.empty()) {
+            a = g_prof.spare.back().first;
+            b = g_prof.spare.back().second;
+            g_prof.spare.pop_back();
+            return true;
+        }
+    }
+    if (hipEventCreate(&a) != hipSuccess) return false;
+    if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return false; }
+    return true;
+}
 
 hipError_t timed(int cls, hipStream_t s, hipError_t (*fn)(const btd::KArgs&, hipStream_t), const btd::KArgs& ka) {
     if (g_prof.cls.load(std::memory_order_relaxed) != cls) return fn(ka, s);
     hipEvent_t a, b;
-    if (hipEventCreate(&a) != hipSuccess) return hipErrorUnknown;
-    if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return hipErrorUnknown; }
+    if (!profile_pair(a, b)) return hipErrorUnknown;
     (void)hipEventRecord(a, s);
     hipError_t err = fn(ka, s);
     (void)hipEventRecord(b, s);
@@ -315,6 +331,7 @@ int enqueue_factor(btd_plan_s* p, hipStream_t s) {
         ka.status = p->status;
         ka.c0 = 0;
         ka.nc = LP.P;
+        ka.lowp = (p->desc.prec == BTD_PREC_F32_REFINE && l == 0) ? 1 : 0;
         BTD_TRY(btd::launch_write_ints((int*)(p->ws + LP.off_sep), LP.sep.data(), LP.P + 1, s));
         // chunk groups, each on its own stream (one group: the caller's stream)
         int G = chunk_groups(LP.P);
@@ -525,6 +542,81 @@ int btd_solve(btd_plan_t plan, int32_t nrhs, const double* F, double* X, void* s
     return enqueue_solve_level(plan, 0, nrhs, F, X, (char*)solve_ws, 0, (hipStream_t)stream);
 }
 
+// Workspace of btd_solve_refine: the solve workspace, the residual vector
+// [N][M][R], the residual kernels' partial sums and the R column norms.
+struct RefineLayout {
+    size_t solve, rvec, part, norms, total;
+};
+RefineLayout refine_layout(const btd_plan_s* p, int R) {
+    RefineLayout L{};
+    const int N = p->desc.N, M = p->desc.M;
+    L.solve = 0;
+    L.rvec = align_up(solve_bytes_for(p->levels, R));
+    L.part = L.rvec + align_up(sizeof(double) * (size_t)N * M * R);
+    L.norms = L.part + align_up(btd_residual_work_bytes(N, M, R));
+    L.total = L.norms + align_up(sizeof(double) * (size_t)R);
+    return L;
+}
+
+size_t btd_refine_work_bytes(btd_plan_t plan, int32_t nrhs) {
+    if (!plan || nrhs < 1 || nrhs > plan->desc.max_nrhs) return 0;
+    return refine_layout(plan, nrhs).total;
+}
+
+int btd_solve_refine(btd_plan_t plan, int32_t nrhs, const double* F, double* X, void* work, size_t work_bytes,
+                     double tol, int32_t max_iter, int32_t* iters, double* resid, void* stream) {
+    if (!plan) return -1;
+    if (nrhs < 1 || nrhs > plan->desc.max_nrhs) return -2;
+    if (!F) return -3;
+    if (!X || X == F) return -4;
+    if (!work || ((uintptr_t)work % kAlign) != 0) return -5;
+    const RefineLayout lay = refine_layout(plan, nrhs);
+    if (work_bytes < lay.total) return -6;
+    if (!(tol > 0.0) || max_iter < 0) return -7;
+    int rc = ensure_configured();
+    if (rc != BTD_OK) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    char* w = (char*)work;
+    double* rv = (double*)(w + lay.rvec);
+    double* part = (double*)(w + lay.part);
+    double* norms = (double*)(w + lay.norms);
+    const int N = plan->desc.N, M = plan->desc.M, R = nrhs;
+    const size_t n = (size_t)N * M * R;
+    rc = enqueue_rhs_check(plan, R, F, s);
+    if (rc != BTD_OK) return rc;
+    rc = enqueue_solve_level(plan, 0, R, F, X, w + lay.solve, 0, s);
+    if (rc != BTD_OK) return rc;
+    std::vector<double> h(R);
+    int it = 0;
+    double worst = 0.0;
+    while (true) {
+        hipEvent_t ea = nullptr, eb = nullptr;
+        if (g_prof.cls.load(std::memory_order_relaxed) == BTD_KC_RESIDUAL) {
+            if (!profile_pair(ea, eb)) return BTD_ERR_LAUNCH;
+            (void)hipEventRecord(ea, s);
+        }
+        BTD_TRY(btd::launch_residual(N, M, R, plan->A, plan->B, plan->C, X, F, norms, part, s, rv));
+        if (ea) {
+            (void)hipEventRecord(eb, s);
+            std::lock_guard<std::mutex> lock(g_prof.mu);
+            g_prof.ev.emplace_back(ea, eb);
+        }
+        BTD_TRY(hipMemcpyAsync(h.data(), norms, sizeof(double) * R, hipMemcpyDeviceToHost, s));
+        BTD_TRY(hipStreamSynchronize(s));
+        worst = 0.0;
+        for (int c = 0; c < R; ++c) worst = std::isnan(h[c]) || h[c] > worst ? h[c] : worst;
+        if (worst <= tol || it >= max_iter || std::isnan(worst)) break;
+        // correction: D = A^{-1} r (in place on the residual vector), X += D
+        rc = enqueue_solve_level(plan, 0, R, rv, rv, w + lay.solve, 0, s);
+        if (rc != BTD_OK) return rc;
+        BTD_TRY(btd::launch_add(X, rv, n, s));
+        ++it;
+    }
+    if (iters) *iters = it;
+    if (resid) *resid = worst;
+    return worst <= tol ? BTD_OK : BTD_ERR_NOT_CONVERGED;
+}
+
 int btd_solve_noalloc(btd_plan_t plan, int32_t nrhs, const double* F, double* X, void* stream) {
     if (!plan) return -1;
     if (nrhs < 1 || nrhs > plan->desc.max_nrhs) return -2;
@@ -661,7 +753,7 @@ int btd_residual(int32_t N, int32_t M, int32_t R, const double* A, const double*
     hipStream_t s = (hipStream_t)stream;
     hipEvent_t a = nullptr, b = nullptr;
     if (g_prof.cls.load(std::memory_order_relaxed) == BTD_KC_RESIDUAL) {
-        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return BTD_ERR_LAUNCH;
+        if (!profile_pair(a, b)) return BTD_ERR_LAUNCH;
         (void)hipEventRecord(a, s);
     }
     BTD_TRY(btd::launch_residual(N, M, R, A, B, C, X, F, out, (double*)work, s));
@@ -757,8 +849,7 @@ int btd_profile_read(double* total_ms, int64_t* launches) {
             rc = BTD_ERR_LAUNCH;
         tot += ms;
         ++n;
-        (void)hipEventDestroy(pr.first);
-        (void)hipEventDestroy(pr.second);
+        g_prof.spare.push_back(pr);
     }
     g_prof.ev.clear();
     if (total_ms) *total_ms = tot;
@@ -779,6 +870,7 @@ const char* btd_status_string(int code) {
         case BTD_ERR_NONFINITE: return "non-finite pivot in the LU of a diagonal block";
         case BTD_ERR_LAUNCH: return "HIP launch or copy failed";
         case BTD_ERR_SCRATCH: return "solve needs more scratch than the static buffer of btd_solve_noalloc";
+        case BTD_ERR_NOT_CONVERGED: return "iterative refinement did not reach the tolerance";
         default: return code < 0 ? "invalid argument" : "unknown status";
     }
 }
