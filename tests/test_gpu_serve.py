@@ -20,10 +20,9 @@ def test_results_same_alone_and_in_the_mix():
     sizes = [(40, 16), (64, 32), (100, 24), (33, 8)]
     reqs = serve.make_load(torch, rate=600.0, seconds=0.08, seed=7, sizes=sizes)
     assert len(reqs) >= 20
-    fmax = max(btd.workspace_bytes(N, M, max(1, min(64, (N + 1) // 8)), serve.DEPTH, serve.MAX_NRHS, None,
-                                   serve.COUPLING_ROWS)[0] for N, M in sizes)
-    smax = max(btd.workspace_bytes(N, M, max(1, min(64, (N + 1) // 8)), serve.DEPTH, serve.MAX_NRHS, None,
-                                   serve.COUPLING_ROWS)[1] for N, M in sizes)
+    pool = {r.system.name: r.system for r in reqs}
+    fmax = max(serve.footprint(sy, serve.MAX_NRHS)[0] for sy in pool.values())
+    smax = max(sum(serve.footprint(sy, serve.MAX_NRHS)[1]) for sy in pool.values())
     budget = 2 * fmax + 3 * smax          # room for about two resident factorizations
     print(f"serve {len(reqs)} requests, budget {budget} bytes", flush=True)
     finished, counters = serve.serve(reqs, budget, slots=3, keep_results=True)
@@ -32,8 +31,10 @@ def test_results_same_alone_and_in_the_mix():
     assert counters["peak_bytes"] <= budget
     refs = {}
     for r in finished:
-        A, B, C, P = r.system
-        plan = btd.factor(A, B, C, P=P, depth=serve.DEPTH, max_nrhs=serve.MAX_NRHS,
+        sy = r.system
+        A, B, C, P = sy.A, sy.B, sy.C, sy.P
+        assert r.res is not None and r.res <= 1e-12, (r.rid, r.res)
+        plan = btd.factor(A, B, C, P=P, depth=serve.DEPTH, max_nrhs=sy.max_nrhs,
                           coupling_rows=serve.COUPLING_ROWS)
         X = plan.solve(r.F)
         assert plan.info() == (0, -1, -1)
@@ -67,14 +68,53 @@ def test_reused_system_is_never_evicted_for_itself():
     systems = []
     for q in range(2):
         A, B, C, _ = serve.inputs.diag_dominant(N, M, 1, seed=4100 + q)
-        systems.append(tuple(torch.from_numpy(a).cuda() for a in (A, B, C)) + (P,))
+        systems.append(serve.System(f"s{q}", *(torch.from_numpy(a).cuda() for a in (A, B, C)), P, serve.MAX_NRHS,
+                                    (1,)))
     rng = np.random.default_rng(3)
     keys = [0, 1, 0, 0, 1, 0]
     reqs = [serve.Request(i, k, 0.0, systems[k], torch.from_numpy(rng.standard_normal((N, M, 1))).cuda())
             for i, k in enumerate(keys)]
-    f, sb = btd.workspace_bytes(N, M, P, serve.DEPTH, serve.MAX_NRHS, None, serve.COUPLING_ROWS)
+    f, parts = serve.footprint(systems[0], 1)
+    sb = sum(parts)                       # one request's own arrays
     budget = 2 * f + sb + sb // 2
     finished, counters = serve.serve(reqs, budget, slots=2, keep_results=True)
     assert len(finished) == len(reqs)
     assert (counters["factored"], counters["reused"], counters["evictions"]) == (3, 3, 1), counters
     assert counters["peak_bytes"] <= budget
+
+
+def test_serving_mix_families_match_oracle():
+    """The serving mix's three families at reduced sizes (Faddeev-type
+    banded blocks; dense blocks with shift 1.5 and 1 or 64 right-hand sides;
+    uneven systems with M in {32, 64, 128, 192} and 1, 8 or 32 right-hand
+    sides), arriving faster than they are served, 30% of them reusing a
+    resident factorization: every result against the FP64 oracle."""
+    import numpy as np
+    torch = require_gpu()
+    rng = np.random.default_rng(21)
+    dev = "cuda"
+
+    def system(name, arrays, P, max_nrhs, counts):
+        return serve.System(name, *(torch.from_numpy(a).to(dev) for a in arrays[:3]), P, max_nrhs, counts)
+
+    pool = {"faddeev": [system("faddeev", serve.inputs.faddeev_like(256, 128, 1, seed=22), 32, 4, (4,))],
+            "large": [system("large", serve.inputs.diag_dominant(240, 256, 1, seed=23, shift=1.5), 32, 64, (1, 64))],
+            "uneven": []}
+    for q in range(5):
+        N, M = int(rng.integers(32, 300)), int(rng.choice([32, 64, 128, 192]))
+        pool["uneven"].append(system(f"uneven{q}", serve.inputs.diag_dominant(N, M, 1, seed=3100 + q),
+                                     max(1, min(256, (N + 1) // 8)), 32, (1, 8, 32)))
+    reqs = serve.make_load(torch, rate=300.0, seconds=0.12, seed=24, pool=pool)
+    assert len(reqs) >= 15
+    print(f"serve mix: {len(reqs)} requests", flush=True)
+    finished, counters = serve.serve(reqs, 64 * 2**30, slots=4, keep_results=True)
+    assert len(finished) == len(reqs) and counters["reused"] > 0, counters
+    host = {}
+    for r in finished:
+        sy = r.system
+        if sy.name not in host:
+            host[sy.name] = tuple(t.cpu().numpy() for t in (sy.A, sy.B, sy.C))
+        A, B, C = host[sy.name]
+        F = r.F.cpu().numpy()
+        assert r.res <= 1e-12, (r.rid, sy.name, r.res)
+        assert_parity(r.X.cpu().numpy(), oracle.dm_solve(A, B, C, F, min(sy.P, 16), depth=1), 1e-10)
