@@ -14,7 +14,8 @@ right-hand-side columns, ``P`` subsystems.  Arrays are numpy float64,
 Functions and the passage each follows:
   ta_solve       Thomas algorithm, Sec. 3 (explicit inverses G_i, Sec. 4).
   dm_solve       DM, Sec. 2 (Eqs. e220-e232, endSolution); recursion on the
-                 coupling system, Sec. 4.2 (Eq. DMrec1).
+                 coupling system, Sec. 4.2 (Eq. DMrec1); recursion into the
+                 subsystems (J sub-subsystems, Sec. 4.2.2) and both.
   gepp_solve     dense Gaussian elimination with partial pivoting.
   residual       ||F - A X||_2 / ||F||_2 per column.
   partition      equal-split separators (Sec. 2 and Sec. 5).
@@ -61,7 +62,7 @@ def lib():
         L.or_partition.argtypes = [ctypes.c_int, ctypes.c_int, ip]
         L.or_default_m.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
         L.or_ta_solve.argtypes = [ctypes.c_int] * 3 + [dp] * 5 + [ctypes.POINTER(Counter), ip, ip]
-        L.or_dm_solve.argtypes = ([ctypes.c_int] * 4 + [ip, ctypes.c_int] + [dp] * 5 +
+        L.or_dm_solve.argtypes = ([ctypes.c_int] * 4 + [ip, ctypes.c_int, ctypes.c_int] + [dp] * 5 +
                                   [ctypes.POINTER(_Aux), ctypes.POINTER(Counter), ctypes.c_int, ip, ip])
         L.or_gepp_solve.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, dp]
         L.or_residual.argtypes = [ctypes.c_int] * 3 + [dp] * 6
@@ -163,8 +164,10 @@ def ta_solve(A, B, C, F, counter=None):
     return X
 
 
-def dm_solve(A, B, C, F, P, seps=None, depth=0, counter=None, want_aux=False, nthreads=0):
-    """DM solve.  Returns X, or (X, aux dict) with want_aux.
+def dm_solve(A, B, C, F, P, seps=None, depth=0, counter=None, want_aux=False, nthreads=0, J=1):
+    """DM solve.  Returns X, or (X, aux dict) with want_aux.  J >= 2 solves
+    every subsystem by the DM with J sub-subsystems (Sec. 4.2.2; D, E, y of
+    aux are then not filled).
 
     aux holds D, E, ZL, ZR (shape (N, M, M), chunk rows only, zero elsewhere),
     y and z (shape (N, M, R)), Hd, Hb, Hc (shape (P-1, M, M)), fhat and h
@@ -186,7 +189,7 @@ def dm_solve(A, B, C, F, P, seps=None, depth=0, counter=None, want_aux=False, nt
         sep_arr = (ctypes.c_int * max(len(seps), 1))(*[int(s) for s in seps])
         assert len(seps) == P - 1
     row, col = ctypes.c_int(-1), ctypes.c_int(-1)
-    s = lib().or_dm_solve(N, M, R, P, sep_arr, depth, _ptr(A), _ptr(B), _ptr(C), _ptr(F), _ptr(X),
+    s = lib().or_dm_solve(N, M, R, P, sep_arr, depth, int(J), _ptr(A), _ptr(B), _ptr(C), _ptr(F), _ptr(X),
                           ctypes.byref(aux_c) if aux_c is not None else None,
                           ctypes.byref(counter) if counter is not None else None,
                           int(nthreads), ctypes.byref(row), ctypes.byref(col))

@@ -30,6 +30,8 @@
  *   or_dm_solve     -- the DM (Sec. 2, Eqs. e220-e232 and endSolution), with
  *                      the coupling system solved by the TA or recursively by
  *                      the DM (Sec. 4.2, Eq. DMrec1).
+ *   or_dm_chunk     -- a subsystem solved by the DM itself (recursion into
+ *                      the subsystems, Sec. 4.2.2, Eqs. DMrec121-DMrec122).
  *   or_gepp_solve   -- textbook dense Gaussian elimination with partial
  *                      pivoting (first maximum wins), for tiny inputs.
  *   or_residual     -- ||F - A X||_2 / ||F||_2 per RHS column.
@@ -250,6 +252,127 @@ static int or_ta_chunk(int nk, int M, int R, const double *A, const double *B, c
     return status;
 }
 
+int or_partition(int N, int P, int *seps);
+
+/* A subsystem of nk rows solved by the DM itself with J sub-subsystems
+ * (recursion into the independent subsystems, Sec. 4.2.2), for the same
+ * right-hand sides or_ta_chunk takes: the dense F (R columns), the block sL
+ * seeded at the subsystem's first row and the block sR seeded at its last
+ * row (either may be NULL).  Writes z, ZL, ZR like or_ta_chunk, for every
+ * row of the subsystem.  Zero blocks of the seeded columns are skipped the
+ * way the paper counts them (Eqs. DMrec121, DMrec1212, DMrec122): the sL
+ * columns enter only the first sub-subsystem (top-seeded there, in place of
+ * its missing left spike) and the first row of the inner coupling system;
+ * the sR columns only the last sub-subsystem (bottom-seeded, in place of its
+ * missing right spike) and the last row of the inner coupling system.  The
+ * inner coupling system is solved by the Thomas algorithm.  J < 2, or a
+ * subsystem too short for J parts, is the plain Thomas algorithm.
+ * Returns 0, or 1 + the failing row within the subsystem. */
+static int or_dm_chunk(int nk, int M, int R, const double *A, const double *B, const double *C,
+                       const double *F, const double *sL, const double *sR, double *z, double *ZL,
+                       double *ZR, int J, or_counter_t *cnt, int *bad_col) {
+    if (J < 2 || 2 * J - 1 > nk)
+        return or_ta_chunk(nk, M, R, A, B, C, F, sL, sR, z, ZL, ZR, NULL, NULL, NULL, cnt, bad_col);
+    const size_t MM = (size_t)M * M, MR = (size_t)M * R;
+    const int Jc = J - 1;
+    int *sp = (int *)malloc(sizeof(int) * (size_t)Jc);
+    or_partition(nk, J, sp);
+    /* per row of the subsystem: the inner spikes, the sub-subsystem solution
+     * of F, and of the seeded columns (nonzero in the first / last
+     * sub-subsystem only) */
+    double *iZL = (double *)calloc(MM * (size_t)nk, sizeof(double));
+    double *iZR = (double *)calloc(MM * (size_t)nk, sizeof(double));
+    double *zf = (double *)calloc(MR * (size_t)nk, sizeof(double));
+    double *yL = sL ? (double *)calloc(MM * (size_t)nk, sizeof(double)) : NULL;
+    double *yR = sR ? (double *)calloc(MM * (size_t)nk, sizeof(double)) : NULL;
+    double *Hd = (double *)calloc(MM * (size_t)Jc, sizeof(double));
+    double *Hb = (double *)calloc(MM * (size_t)Jc, sizeof(double));
+    double *Hc = (double *)calloc(MM * (size_t)Jc, sizeof(double));
+    double *fF = (double *)calloc(MR * (size_t)Jc, sizeof(double));
+    double *fL = (double *)calloc(MM, sizeof(double));
+    double *fR = (double *)calloc(MM, sizeof(double));
+    double *hF = (double *)calloc(MR * (size_t)Jc, sizeof(double));
+    double *hL = (double *)calloc(MM * (size_t)Jc, sizeof(double));
+    double *hR = (double *)calloc(MM * (size_t)Jc, sizeof(double));
+    int status = 0;
+    long long c_mm = 0, c_mr = 0;
+    /* Eq. e231 within the subsystem: every sub-subsystem by the Thomas
+     * algorithm with its own spikes; the outer seeds take the place of the
+     * spike a first (last) sub-subsystem does not have */
+    for (int i = 0; i < J && !status; ++i) {
+        const int r = (i == 0) ? 0 : sp[i - 1] + 1, e = (i == J - 1) ? nk - 1 : sp[i] - 1, n = e - r + 1;
+        const double *tL = (i == 0) ? sL : B + (size_t)r * MM;
+        const double *tR = (i == J - 1) ? sR : C + (size_t)e * MM;
+        double *oL = (i == 0) ? (yL ? yL + (size_t)r * MM : NULL) : iZL + (size_t)r * MM;
+        double *oR = (i == J - 1) ? (yR ? yR + (size_t)r * MM : NULL) : iZR + (size_t)r * MM;
+        int bc = -1;
+        int s = or_ta_chunk(n, M, R, A + (size_t)r * MM, B + (size_t)r * MM, C + (size_t)r * MM, F + (size_t)r * MR,
+                            tL, tR, zf + (size_t)r * MR, oL, oR, NULL, NULL, NULL, cnt, &bc);
+        if (s) { status = r + s; if (bad_col) *bad_col = bc; }
+    }
+    if (!status) {
+        /* the inner coupling system (Eq. e2311 within the subsystem); the
+         * seeded columns' right-hand side has one nonzero block each */
+        for (int j = 0; j < Jc; ++j) {
+            const int q = sp[j], e = q - 1, r = q + 1;
+            const double *Bq = B + (size_t)q * MM, *Cq = C + (size_t)q * MM;
+            memcpy(Hd + (size_t)j * MM, A + (size_t)q * MM, sizeof(double) * MM);
+            mm(M, M, M, -1.0, Bq, M, iZR + (size_t)e * MM, M, 1.0, Hd + (size_t)j * MM, M); c_mm++;
+            mm(M, M, M, -1.0, Cq, M, iZL + (size_t)r * MM, M, 1.0, Hd + (size_t)j * MM, M); c_mm++;
+            if (j >= 1) { mm(M, M, M, -1.0, Bq, M, iZL + (size_t)e * MM, M, 0.0, Hb + (size_t)j * MM, M); c_mm++; }
+            if (j + 1 <= J - 2) { mm(M, M, M, -1.0, Cq, M, iZR + (size_t)r * MM, M, 0.0, Hc + (size_t)j * MM, M); c_mm++; }
+            memcpy(fF + (size_t)j * MR, F + (size_t)q * MR, sizeof(double) * MR);
+            mm(M, M, R, -1.0, Bq, M, zf + (size_t)e * MR, R, 1.0, fF + (size_t)j * MR, R); c_mr++;
+            mm(M, M, R, -1.0, Cq, M, zf + (size_t)r * MR, R, 1.0, fF + (size_t)j * MR, R); c_mr++;
+        }
+        if (sL) { mm(M, M, M, -1.0, B + (size_t)sp[0] * MM, M, yL + (size_t)(sp[0] - 1) * MM, M, 0.0, fL, M); c_mm++; }
+        if (sR) {
+            const int q = sp[Jc - 1];
+            mm(M, M, M, -1.0, C + (size_t)q * MM, M, yR + (size_t)(q + 1) * MM, M, 0.0, fR, M); c_mm++;
+        }
+        /* Eq. e232 within the subsystem by the Thomas algorithm: F columns
+         * dense, sL columns seeded at its first row, sR columns at its last */
+        int bc = -1;
+        int s = or_ta_chunk(Jc, M, R, Hd, Hb, Hc, fF, sL ? fL : NULL, sR ? fR : NULL, hF, sL ? hL : NULL,
+                            sR ? hR : NULL, NULL, NULL, NULL, cnt, &bc);
+        if (s) { status = sp[s - 1] + 1; if (bad_col) *bad_col = bc; }
+    }
+    if (!status) {
+        /* Eq. endSolution within the subsystem for the three column groups */
+        for (int j = 0; j < Jc; ++j) {
+            memcpy(z + (size_t)sp[j] * MR, hF + (size_t)j * MR, sizeof(double) * MR);
+            if (sL) memcpy(ZL + (size_t)sp[j] * MM, hL + (size_t)j * MM, sizeof(double) * MM);
+            if (sR) memcpy(ZR + (size_t)sp[j] * MM, hR + (size_t)j * MM, sizeof(double) * MM);
+        }
+        for (int i = 0; i < J; ++i) {
+            const int r = (i == 0) ? 0 : sp[i - 1] + 1, e = (i == J - 1) ? nk - 1 : sp[i] - 1;
+            for (int row = r; row <= e; ++row) {
+                const double *zl = iZL + (size_t)row * MM, *zr = iZR + (size_t)row * MM;
+                double *zi = z + (size_t)row * MR;
+                memcpy(zi, zf + (size_t)row * MR, sizeof(double) * MR);
+                if (i > 0) { mm(M, M, R, -1.0, zl, M, hF + (size_t)(i - 1) * MR, R, 1.0, zi, R); c_mr++; }
+                if (i < J - 1) { mm(M, M, R, -1.0, zr, M, hF + (size_t)i * MR, R, 1.0, zi, R); c_mr++; }
+                if (sL) {
+                    double *o = ZL + (size_t)row * MM;
+                    memcpy(o, yL + (size_t)row * MM, sizeof(double) * MM);
+                    if (i > 0) { mm(M, M, M, -1.0, zl, M, hL + (size_t)(i - 1) * MM, M, 1.0, o, M); c_mm++; }
+                    if (i < J - 1) { mm(M, M, M, -1.0, zr, M, hL + (size_t)i * MM, M, 1.0, o, M); c_mm++; }
+                }
+                if (sR) {
+                    double *o = ZR + (size_t)row * MM;
+                    memcpy(o, yR + (size_t)row * MM, sizeof(double) * MM);
+                    if (i > 0) { mm(M, M, M, -1.0, zl, M, hR + (size_t)(i - 1) * MM, M, 1.0, o, M); c_mm++; }
+                    if (i < J - 1) { mm(M, M, M, -1.0, zr, M, hR + (size_t)i * MM, M, 1.0, o, M); c_mm++; }
+                }
+            }
+        }
+    }
+    cnt_add(cnt, 0, c_mm, c_mr);
+    free(sp); free(iZL); free(iZR); free(zf); free(yL); free(yR); free(Hd); free(Hb); free(Hc);
+    free(fF); free(fL); free(fR); free(hF); free(hL); free(hR);
+    return status;
+}
+
 /* Equal-split separators: P-1 rows q_0 < ... < q_{P-2} (0-based), none in
  * the first or the last row, every subsystem non-empty.  Subsystem sizes are
  * floor((N-P+1)/P), the first (N-P+1) mod P subsystems one row longer.
@@ -299,12 +422,14 @@ int or_ta_solve(int N, int M, int R, const double *A, const double *B, const dou
 /* Decomposition method (Sec. 2).  seps: P-1 0-based separator rows or NULL
  * for the equal split; depth: number of DM levels applied to the coupling
  * system (0 = Thomas algorithm, Eq. e232; >= 1 = recursive DM, Eq. DMrec1,
- * with or_default_m subsystems).  P == 1 is the plain Thomas algorithm.
+ * with or_default_m subsystems); J >= 2: every subsystem solved by the DM
+ * with J equal sub-subsystems (recursion into the subsystems, Sec. 4.2.2;
+ * with depth >= 1 both recursions).  P == 1 is the plain Thomas algorithm.
  * nthreads > 0 fixes the OpenMP team for the independent subsystems. */
-int or_dm_solve(int N, int M, int R, int P, const int *seps_in, int depth, const double *A,
+int or_dm_solve(int N, int M, int R, int P, const int *seps_in, int depth, int J, const double *A,
                 const double *B, const double *C, const double *F, double *X, or_aux_t *aux,
                 or_counter_t *cnt, int nthreads, int *bad_row, int *bad_col) {
-    if (N < 1 || M < 1 || R < 1 || P < 1 || depth < 0) return OR_ERR_ARG;
+    if (N < 1 || M < 1 || R < 1 || P < 1 || depth < 0 || J < 1) return OR_ERR_ARG;
     const size_t MM = (size_t)M * M, MR = (size_t)M * R;
     if (P == 1) {
         int s = or_ta_chunk(N, M, R, A, B, C, F, NULL, NULL, X, NULL, NULL, aux ? aux->D : NULL,
@@ -337,11 +462,15 @@ int or_dm_solve(int N, int M, int R, int P, const int *seps_in, int depth, const
         const double *sL = (k > 0) ? B + (size_t)r * MM : NULL;     /* couples to h^{k-1} */
         const double *sR = (k < P - 1) ? C + (size_t)e * MM : NULL; /* couples to h^k     */
         int bc = -1;
-        int s = or_ta_chunk(nk, M, R, A + (size_t)r * MM, B + (size_t)r * MM, C + (size_t)r * MM,
-                            F + (size_t)r * MR, sL, sR, z + (size_t)r * MR, ZL + (size_t)r * MM,
-                            ZR + (size_t)r * MM, aux && aux->D ? aux->D + (size_t)r * MM : NULL,
-                            aux && aux->E ? aux->E + (size_t)r * MM : NULL,
-                            aux && aux->y ? aux->y + (size_t)r * MR : NULL, cnt, &bc);
+        int s = (J >= 2)
+                    ? or_dm_chunk(nk, M, R, A + (size_t)r * MM, B + (size_t)r * MM, C + (size_t)r * MM,
+                                  F + (size_t)r * MR, sL, sR, z + (size_t)r * MR, ZL + (size_t)r * MM,
+                                  ZR + (size_t)r * MM, J, cnt, &bc)
+                    : or_ta_chunk(nk, M, R, A + (size_t)r * MM, B + (size_t)r * MM, C + (size_t)r * MM,
+                                  F + (size_t)r * MR, sL, sR, z + (size_t)r * MR, ZL + (size_t)r * MM,
+                                  ZR + (size_t)r * MM, aux && aux->D ? aux->D + (size_t)r * MM : NULL,
+                                  aux && aux->E ? aux->E + (size_t)r * MM : NULL,
+                                  aux && aux->y ? aux->y + (size_t)r * MR : NULL, cnt, &bc);
         if (s) {
 #ifdef _OPENMP
 #pragma omp critical
@@ -392,7 +521,7 @@ int or_dm_solve(int N, int M, int R, int P, const int *seps_in, int depth, const
      * TA or, for depth >= 1, by the DM itself (Eq. DMrec1). */
     int m = (depth > 0) ? or_default_m(P, M, R) : 1;
     int sb = -1, sc = -1;
-    int s = or_dm_solve(Pc, M, R, m, NULL, depth > 0 ? depth - 1 : 0, Hd, Hb, Hc, fh, h, NULL, cnt,
+    int s = or_dm_solve(Pc, M, R, m, NULL, depth > 0 ? depth - 1 : 0, 1, Hd, Hb, Hc, fh, h, NULL, cnt,
                         nthreads, &sb, &sc);
     if (s != OR_OK) {
         if (bad_row) *bad_row = (sb >= 0 && sb < Pc) ? seps[sb] : -1;

@@ -90,3 +90,56 @@ def p3dmrec4(N, n, l):
     M = (N + 1) / J**2 * (a3 / a7)
     m = math.sqrt(M * (7 * n**3 + 5 * n**2 * l) / (3 * (n**3 + n**2 * l)))
     return M, J, m
+
+
+def dm_rec12(Ls, k, P):
+    """Solution of Eq. e231 for subsystem k (1-based) of P by the DM with
+    sub-subsystem sizes Ls (recursion into the subsystems, Sec. 4.2.2):
+    Eq. DMrec121 (k = 1), Eq. DMrec1212 (k = P), Eq. DMrec122 (otherwise)."""
+    J = len(Ls)
+    L1, LJ, mid = Ls[0], Ls[-1], sum(Ls[1:-1])
+    if k == 1:
+        return ((5 * L1 - 1) + (8 * LJ - 2) + 9 * mid + (4 * J - 6),
+                (4 * L1 - 1) + (4 * LJ - 1) + 5 * mid + (3 * J - 5))
+    if k == P:
+        return ((8 * L1 - 2) + (7 * LJ - 3) + 9 * mid + (6 * J - 10),
+                (4 * L1 - 1) + (4 * LJ - 1) + 5 * mid + (3 * J - 5))
+    return ((9 * L1 - 2) + (9 * LJ - 2) + 11 * mid + (7 * J - 11),
+            (4 * L1 - 1) + (4 * LJ - 1) + 5 * mid + (3 * J - 5))
+
+
+def dm_total_subrec(Ls_per_subsystem, coupling=None):
+    """Total operations of the DM whose subsystems are solved by the DM
+    (sizes Ls_per_subsystem[k] of their sub-subsystems): Eqs. DMrec121-122
+    summed over the subsystems, plus the coupling products and the recovery
+    of Tab. 2 and the coupling system ((3P-5)(n^3+n^2 l), or `coupling`)."""
+    P = len(Ls_per_subsystem)
+    parts = [dm_rec12(Ls, k, P) for k, Ls in enumerate(Ls_per_subsystem, 1)]
+    Nks = [sum(Ls) + len(Ls) - 1 for Ls in Ls_per_subsystem]
+    parts += [dm_table2_coupling_products(k, P) for k in range(1, P + 1)]
+    parts += [dm_table2_recovery(k, P, Nk) for k, Nk in enumerate(Nks, 1)]
+    parts.append(coupling if coupling is not None else (3 * P - 5, 3 * P - 5))
+    return tuple(map(sum, zip(*parts)))
+
+
+def dmrec3(N, M, J, n, l):
+    """Eq. DMrec3: serial operations with M equal subsystems of J equal
+    sub-subsystems each (P = M J processors), the coupling system by the
+    Thomas algorithm."""
+    N1 = (N - M + 1) / M
+    N2 = (N1 - J + 1) / J
+    return ((11 * n**3 + 5 * n**2 * l) * N2 + (n**3 * (7 * J - 11) + n**2 * l * (3 * J - 5))
+            + 4 * n**3 + 2 * n**2 * l + (n**3 + n**2 * l) * (3 * M - 5) + 2 * n**2 * l * N1)
+
+
+def p3dmrec3(N, n, l):
+    """Recursion into the subsystems with P free: J the real positive root of
+    the quartic Eq. P3DMrec3, M from Eq. P2DMrec3.  Returns (M, J)."""
+    a11 = 11 * n**3 + 5 * n**2 * l
+    a7 = 7 * n**3 + 3 * n**2 * l
+    two = 2 * n**2 * l
+    c3 = a11 / two
+    c0 = -(N + 1) * 3 * (n**3 + n**2 * l) * a11**2 / (a7**2 * two)
+    roots = np.roots([1.0, c3, 0.0, 0.0, c0])
+    J = max(r.real for r in roots if abs(r.imag) < 1e-9 and r.real > 0)
+    return (N + 1) / J**2 * (a11 / a7), J

@@ -420,3 +420,53 @@ def test_suppmatr_m_minimises_counted_operations(n, l):
     assert np.isclose(costmodel.suppmatr_m(300, 10**9, 1), np.sqrt(7 * 300 / 3), rtol=1e-8)
     assert np.isclose(3 * costmodel.suppmatr_m(21, 10**9, 0), 21.0, rtol=1e-12)
     assert 3 * costmodel.suppmatr_m(20, 10**9, 0) > 20.0
+
+
+# ---------------------------------------------------------------- recursion into the subsystems
+
+def _sizes(N, P):
+    b = [-1] + oracle.partition(N, P) + [N]
+    return [b[k + 1] - b[k] - 1 for k in range(P)]
+
+
+@pytest.mark.parametrize("N,P,J,depth", [(40, 3, 2, 0), (63, 4, 3, 0), (90, 5, 4, 0), (121, 6, 2, 0), (70, 2, 5, 0),
+                                         (200, 12, 3, 1)])
+def test_subsystem_recursion_matches_dense_and_counts(N, P, J, depth):
+    """Every subsystem solved by the DM with J sub-subsystems (Sec. 4.2.2):
+    the solution of the dense system, the same outer coupling system as the
+    plain method (it is the Schur complement onto the separator rows, however
+    the subsystems are solved), and the operation counter equal to Eqs.
+    DMrec121 (first subsystem), DMrec1212 (last) and DMrec122 (the others)
+    plus the coupling products and recovery of Tab. 2 and the coupling
+    system (Thomas algorithm, or Eq. DMrec1 with depth 1)."""
+    A, B, C, F = rand_system(N, 2, 2, seed=70 + N)
+    cnt = oracle.Counter()
+    X, aux = oracle.dm_solve(A, B, C, F, P, depth=depth, J=J, counter=cnt, want_aux=True)
+    assert relerr(X, dense_solve(A, B, C, F)) < 1e-13
+    X0, aux0 = oracle.dm_solve(A, B, C, F, P, depth=depth, want_aux=True)
+    for name in ("Hd", "Hb", "Hc", "fhat", "h"):
+        assert np.allclose(aux[name], aux0[name], rtol=1e-12, atol=1e-13), name
+    Ls = [_sizes(nk, J) for nk in _sizes(N, P)]
+    coupling = None
+    if depth:
+        m = oracle.default_m(P, 2, 2)
+        coupling = costmodel.dm_total(_sizes(P - 1, m))
+    assert (cnt.inv + cnt.mm, cnt.mr) == costmodel.dm_total_subrec(Ls, coupling)
+
+
+def test_subsystem_recursion_j1_is_the_plain_method():
+    A, B, C, F = rand_system(50, 3, 1, seed=80)
+    assert np.array_equal(oracle.dm_solve(A, B, C, F, 4, J=1), oracle.dm_solve(A, B, C, F, 4))
+
+
+def test_dmrec3_optimum_is_the_quartic_root():
+    """Eq. P3DMrec3 (J, with M from Eq. P2DMrec3) is the minimiser of Eq.
+    DMrec3 over real M and J (P = M J free) on a grid, for the parameters of
+    the paper's figures and others."""
+    for N, n, l in [(3071, 400, 1), (3071, 100, 1), (4095, 256, 64), (2047, 128, 4)]:
+        M, J = costmodel.p3dmrec3(N, n, l)
+        Ms = np.linspace(0.5 * M, 1.5 * M, 801)[:, None]
+        Js = np.linspace(0.5 * J, 1.5 * J, 801)[None, :]
+        f = costmodel.dmrec3(N, Ms, Js, n, l)
+        i, j = np.unravel_index(np.argmin(f), f.shape)
+        assert abs(Ms[i, 0] - M) / M < 3e-3 and abs(Js[0, j] - J) / J < 3e-3, (N, n, l, M, J, Ms[i, 0], Js[0, j])
