@@ -59,7 +59,9 @@ def parse():
     ap.add_argument("--prec", choices=("f64", "f32_refine"), default="f64",
                     help="f32_refine: factor products on FP32 MFMA, then iterative refinement to residual 1e-12 "
                          "(FP64 residual, correction and coupling systems); the step is factor + refined solve")
-    ap.add_argument("--sweep", choices=("faddeev", "P"), default=None,
+    ap.add_argument("--sub-parts", type=int, default=0,
+                    help="recursion into the subsystems: every subsystem solved with J sub-subsystems (Sec. 4.2.2)")
+    ap.add_argument("--sweep", choices=("faddeev", "P", "J"), default=None,
                     help="instead of the benchmark line: 'faddeev' times the Faddeev-type workload at P in "
                          "{8, 32, 128, 512} x depth {0, 1} (Eq. SuppMatrM coupling split), 'P' the large "
                          "workload at P in {128, 256, 512, 1024} and the split choices; one JSON line each")
@@ -95,7 +97,7 @@ def make_inputs(torch, name, dev):
 class Runner:
     """Direct C-ABI calls with preallocated workspaces (no allocation per step)."""
 
-    def __init__(self, torch, A, B, C, F, P, depth, coupling_rows=0, seps=None, prec="f64"):
+    def __init__(self, torch, A, B, C, F, P, depth, coupling_rows=0, seps=None, prec="f64", sub_parts=0):
         import ctypes
         from paper_1505_06864_amd import btd
         self.ct, self.btd, self.torch = ctypes, btd, torch
@@ -104,8 +106,8 @@ class Runner:
         self.R = F.shape[2]
         self.A, self.B, self.C, self.F = A, B, C, F
         self.prec = prec
-        self.desc, self._keep = btd.make_desc(self.N, self.M, P, depth, self.R, seps, coupling_rows, prec)
-        fb, sb = btd.workspace_bytes(self.N, self.M, P, depth, self.R, seps, coupling_rows)
+        self.desc, self._keep = btd.make_desc(self.N, self.M, P, depth, self.R, seps, coupling_rows, prec, sub_parts)
+        fb, sb = btd.workspace_bytes(self.N, self.M, P, depth, self.R, seps, coupling_rows, sub_parts)
         self.fws, self.fptr = btd._aligned_buffer(fb, A.device)
         self.sws, self.sptr = btd._aligned_buffer(sb, A.device)
         self.fb, self.sb = fb, sb
@@ -329,19 +331,26 @@ def sweep(torch, args):
     dev = torch.device("cuda:0")
     if args.sweep == "faddeev":
         (A, B, C, F), _ = make_inputs(torch, "faddeev", dev)
-        configs = [(P, d, 0) for P in (8, 32, 128, 512) for d in (0, 1)]
+        configs = [(P, d, 0, 0) for P in (8, 32, 128, 512) for d in (0, 1)]
         name = "faddeev"
-    else:
+    elif args.sweep == "P":
         (A, B, C, F), _ = make_inputs(torch, "large", dev)
-        configs = [(P, DEFAULT_DEPTH, 1) for P in (128, 256, 512, 1024)] + [(256, 1, 0), (256, 10, 0), (64, 1, 0)]
+        configs = [(P, DEFAULT_DEPTH, 1, 0) for P in (128, 256, 512, 1024)] + [(256, 1, 0, 0), (256, 10, 0, 0),
+                                                                              (64, 1, 0, 0)]
         name = "large"
+    else:   # recursion into the subsystems: P subsystems of J sub-subsystems (Sec. 4.2.2)
+        (A, B, C, F), _ = make_inputs(torch, "large", dev)
+        configs = [(P, d, crow, J) for (P, J) in ((8, 32), (16, 16), (32, 8), (64, 4), (128, 2))
+                   for (d, crow) in ((0, 0), (10, 1))]
+        name = "large_subsystem_recursion"
     N, M, R = F.shape
-    for P, depth, crow in configs:
-        run = Runner(torch, A, B, C, F, P, depth, crow)
+    for P, depth, crow, J in configs:
+        run = Runner(torch, A, B, C, F, P, depth, crow, sub_parts=J)
         ms, resid = time_steps(torch, run, args.steps)
-        fl = sum(flops.totals(N, M, R, P, depth, R, None, crow))
-        print(json.dumps({"sweep": name, "N": N, "M": M, "R": R, "P": P, "depth": depth, "coupling_rows": crow,
-                          "levels": len(flops.levels(N, M, P, depth, R, None, crow)),
+        fl = sum(flops.totals(N, M, R, P, depth, R, None, crow, J))
+        print(json.dumps({"sweep": name, "N": N, "M": M, "R": R, "P": P, "sub_parts": J, "depth": depth,
+                          "coupling_rows": crow,
+                          "levels": len(flops.levels(N, M, P, depth, R, None, crow, J)),
                           "ms_per_solve": ms, "solves_per_s": 1e3 / ms, "gflop": fl / 1e9,
                           "tflops": fl / (ms * 1e-3) / 1e12, "residual_max": resid}), flush=True)
         del run
@@ -371,7 +380,7 @@ def main():
     crow = args.coupling_rows if args.coupling_rows is not None else DEFAULT_COUPLING_ROWS
     (A, B, C, F), host = make_inputs(torch, args.workload, dev)
     seps = btd.balanced_separators(N, P) if args.balanced else None
-    run = Runner(torch, A, B, C, F, P, depth, crow, seps, args.prec)
+    run = Runner(torch, A, B, C, F, P, depth, crow, seps, args.prec, args.sub_parts)
     mixed = args.prec == "f32_refine"
 
     for _ in range(args.warmup):
@@ -379,7 +388,7 @@ def main():
     torch.cuda.synchronize()
     run.release()
 
-    per = flops.per_class(N, M, R, P, depth, R, seps, crow)
+    per = flops.per_class(N, M, R, P, depth, R, seps, crow, args.sub_parts)
     # pick the kernel class with the largest device time (one untimed step per class)
     class_ms = {}
     for c in btd.KERNEL_CLASSES:
@@ -416,7 +425,7 @@ def main():
     resid = float(run.res.max().item())
     run.release()
 
-    fac, sol = flops.totals(N, M, R, P, depth, R, seps, crow)
+    fac, sol = flops.totals(N, M, R, P, depth, R, seps, crow, args.sub_parts)
     ms_step = wall * 1e3 / args.steps
     # per launch = the class's algorithmic FLOPs over the launches actually made (chunk groups on
     # several streams split one step into several launches)
@@ -440,6 +449,7 @@ def main():
         "config": {"workload": f"{args.workload}: {gen} blocks, N={N}, M={M}, R={R}, "
                                + ("FP64" if not mixed else "FP32 factor products + FP64 refinement to 1e-12"),
                    "N": N, "M": M, "R": R, "P": P, "depth": depth, "coupling_rows": crow,
+                   "sub_parts": args.sub_parts,
                    "partition": "balanced (Sec. 4)" if args.balanced else "equal"},
         "tflops": tflops,
         "frac_fp64_peak": tflops / PEAK_FP64_TFLOPS,
@@ -454,7 +464,8 @@ def main():
                          if v > 0 and per[c][0] > 0},
         "roofline": {"kernel": dom, "bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
-                     "traffic": None if args.balanced else recorded_traffic(dom, args.workload, P, depth, crow),
+                     "traffic": (None if (args.balanced or args.sub_parts or args.prec != "f64")
+                                 else recorded_traffic(dom, args.workload, P, depth, crow)),
                      "avg_launch_ms": dom_avg_ms, "launches": dom_n,
                      "gflop_per_launch": dom_flops_per_launch / 1e9},
     }

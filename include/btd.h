@@ -106,11 +106,26 @@ typedef struct btd_plan_s *btd_plan_t;
  *             when Nc < 3).  Small k trades extra operations for fewer
  *             sequential steps, which is what bounds a recursion level on a
  *             GPU.
+ *   sub_parts J: 0 or 1 = off; J >= 2 = recursion into the subsystems
+ *             (Sec. 4.2.2): every one of the P subsystems is itself solved by
+ *             the method with J equal sub-subsystems (each subsystem needs
+ *             at least 2J-1 rows).  Realised as one level of P*J subsystems
+ *             (the P-1 separators plus J-1 inner separators per subsystem,
+ *             equal split inside each subsystem) whose coupling system is
+ *             split at the P-1 outer separators: its P subsystems are the
+ *             subsystems' own coupling systems (J-1 rows each), and its
+ *             coupling system is the outer one (P-1 rows; the Schur
+ *             complement onto the separators, the same matrix the plain
+ *             method forms), solved according to depth and coupling_rows
+ *             (depth >= 1: both recursions, Sec. 4.2.3).  The solution is
+ *             the same; the intermediate spikes of whole subsystems are not
+ *             formed.
  */
 typedef struct {
     int32_t N, M, P, depth, prec, max_nrhs;
     const int32_t *seps;
     int32_t coupling_rows;
+    int32_t sub_parts;
 } btd_desc_t;
 
 /*
@@ -301,11 +316,13 @@ int btd_residual(int32_t N, int32_t M, int32_t R, const double *A, const double 
  */
 int btd_get_info(btd_plan_t plan, int32_t *status, int32_t *block_row, int32_t *col);
 
-/* Separator rows actually used (P-1 entries into a host array). Returns 0 or -1. */
+/* Separator rows of the P subsystems actually used (P-1 entries into a host
+ * array; with sub_parts the outer separators only). Returns 0 or -1. */
 int btd_plan_separators(btd_plan_t plan, int32_t *seps_out);
 
-/* Subsystem count used for the coupling system at recursion level `level`
- * (level 0 = the top system's P).  Returns the count, or -1 past the last level. */
+/* Subsystem count used for the system at recursion level `level` (level 0 =
+ * the top system: P, or P * sub_parts; level l + 1 = the coupling system of
+ * level l).  Returns the count, or -1 past the last level. */
 int btd_plan_level_parts(btd_plan_t plan, int32_t level);
 
 /* Host-only helpers (no device work): the equal-split separator rows for

@@ -39,7 +39,8 @@ KERNEL_CLASSES = ("fwd_gemm", "getrf", "getrs_factor", "bwd_gemm", "couple", "rh
 class Desc(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int32), ("M", ctypes.c_int32), ("P", ctypes.c_int32),
                 ("depth", ctypes.c_int32), ("prec", ctypes.c_int32), ("max_nrhs", ctypes.c_int32),
-                ("seps", ctypes.POINTER(ctypes.c_int32)), ("coupling_rows", ctypes.c_int32)]
+                ("seps", ctypes.POINTER(ctypes.c_int32)), ("coupling_rows", ctypes.c_int32),
+                ("sub_parts", ctypes.c_int32)]
 
 
 class LevelArrays(ctypes.Structure):
@@ -140,8 +141,8 @@ def _aligned_buffer(nbytes, device, stream=None):
     return buf, ptr
 
 
-def make_desc(N, M, P=1, depth=0, max_nrhs=1, seps=None, coupling_rows=0, prec="f64"):
-    d = Desc(N, M, P, depth, PRECISIONS[prec], max_nrhs, None, coupling_rows)
+def make_desc(N, M, P=1, depth=0, max_nrhs=1, seps=None, coupling_rows=0, prec="f64", sub_parts=0):
+    d = Desc(N, M, P, depth, PRECISIONS[prec], max_nrhs, None, coupling_rows, sub_parts)
     keep = None
     if seps is not None:
         keep = (ctypes.c_int32 * max(len(seps), 1))(*[int(q) for q in seps])
@@ -149,9 +150,9 @@ def make_desc(N, M, P=1, depth=0, max_nrhs=1, seps=None, coupling_rows=0, prec="
     return d, keep
 
 
-def workspace_bytes(N, M, P=1, depth=0, max_nrhs=1, seps=None, coupling_rows=0):
+def workspace_bytes(N, M, P=1, depth=0, max_nrhs=1, seps=None, coupling_rows=0, sub_parts=0):
     """(factor bytes, solve bytes) for a description; raises on an invalid one."""
-    d, _keep = make_desc(N, M, P, depth, max_nrhs, seps, coupling_rows)
+    d, _keep = make_desc(N, M, P, depth, max_nrhs, seps, coupling_rows, sub_parts=sub_parts)
     f, s = ctypes.c_size_t(), ctypes.c_size_t()
     rc = lib().btd_workspace_bytes(ctypes.byref(d), ctypes.byref(f), ctypes.byref(s))
     if rc != BTD_OK:
@@ -197,16 +198,17 @@ def coupling_parts(P, M, R, coupling_rows=0):
 class Plan:
     """A factored system (btd_factor).  Keeps A, B, C and the factor workspace alive."""
 
-    def __init__(self, A, B, C, P=1, depth=0, max_nrhs=1, seps=None, stream=None, coupling_rows=0, prec="f64"):
+    def __init__(self, A, B, C, P=1, depth=0, max_nrhs=1, seps=None, stream=None, coupling_rows=0, prec="f64",
+                 sub_parts=0):
         N, M = A.shape[0], A.shape[1]
         for t, n in ((A, "A"), (B, "B"), (C, "C")):
             _check(t, n, (N, M, M))
         self.N, self.M, self.P, self.depth, self.max_nrhs, self.prec = N, M, P, depth, max_nrhs, prec
         self.device = A.device
         self.A, self.B, self.C = A, B, C
-        fbytes, self.solve_bytes = workspace_bytes(N, M, P, depth, max_nrhs, seps, coupling_rows)
+        fbytes, self.solve_bytes = workspace_bytes(N, M, P, depth, max_nrhs, seps, coupling_rows, sub_parts)
         self._ws, ptr = _aligned_buffer(fbytes, A.device, stream)
-        d, _keep = make_desc(N, M, P, depth, max_nrhs, seps, coupling_rows, prec)
+        d, _keep = make_desc(N, M, P, depth, max_nrhs, seps, coupling_rows, prec, sub_parts)
         h = ctypes.c_void_p()
         rc = lib().btd_factor(ctypes.byref(d), A.data_ptr(), B.data_ptr(), C.data_ptr(), ptr, fbytes,
                               _stream_handle(stream, A.device), ctypes.byref(h))
@@ -263,10 +265,11 @@ class Plan:
         if X is None:
             X = _empty_on(stream, F.shape, dtype=F.dtype, device=F.device)
         _check(X, "X", (self.N, self.M, R))
-        if Fhat is None and self.P > 1:
-            Fhat = _empty_on(stream, (self.P - 1, self.M, R), dtype=torch.float64, device=F.device)
+        P0 = self.level_parts()[0]       # subsystems of the top level (P * sub_parts)
+        if Fhat is None and P0 > 1:
+            Fhat = _empty_on(stream, (P0 - 1, self.M, R), dtype=torch.float64, device=F.device)
         if Fhat is not None:
-            _check(Fhat, "Fhat", (self.P - 1, self.M, R))
+            _check(Fhat, "Fhat", (P0 - 1, self.M, R))
         rc = lib().btd_solve_local(self._h, R, F.data_ptr(), X.data_ptr(),
                                    Fhat.data_ptr() if Fhat is not None else None, _stream_handle(stream, F.device))
         if rc != BTD_OK:
@@ -277,8 +280,9 @@ class Plan:
         """Recovery from the coupling solution H ((P-1, M, R)) into X (btd_solve_finish)."""
         R = X.shape[2]
         _check(X, "X", (self.N, self.M, R))
-        if self.P > 1:
-            _check(H, "H", (self.P - 1, self.M, R))
+        P0 = self.level_parts()[0]
+        if P0 > 1:
+            _check(H, "H", (P0 - 1, self.M, R))
         rc = lib().btd_solve_finish(self._h, R, H.data_ptr() if H is not None else None, X.data_ptr(),
                                     _stream_handle(stream, X.device))
         if rc != BTD_OK:
@@ -370,9 +374,9 @@ class Plan:
             pass
 
 
-def factor(A, B, C, P=1, depth=0, max_nrhs=1, seps=None, stream=None, coupling_rows=0, prec="f64"):
+def factor(A, B, C, P=1, depth=0, max_nrhs=1, seps=None, stream=None, coupling_rows=0, prec="f64", sub_parts=0):
     return Plan(A, B, C, P=P, depth=depth, max_nrhs=max_nrhs, seps=seps, stream=stream, coupling_rows=coupling_rows,
-                prec=prec)
+                prec=prec, sub_parts=sub_parts)
 
 
 def solve_batch(plans, Fs, Xs=None, stream=None, lanes=1):

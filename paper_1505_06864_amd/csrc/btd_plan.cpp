@@ -63,10 +63,23 @@ int coupling_parts(int P, int M, int R, int k = 0) {
     return m;
 }
 
+// Separator table (-1, separators, N) of the caller's P subsystems: the
+// caller's separators or the equal split.
+void outer_separators(const btd_desc_t* d, std::vector<int>& sep) {
+    if (d->seps && d->P > 1) {
+        sep.assign(d->P + 1, 0);
+        sep[0] = -1;
+        sep[d->P] = d->N;
+        for (int k = 0; k < d->P - 1; ++k) sep[k + 1] = d->seps[k];
+    } else {
+        equal_split(d->N, d->P, sep);
+    }
+}
+
 bool valid_desc(const btd_desc_t* d) {
     if (!d) return false;
     if (d->N < 1 || d->M < 1 || d->M > BTD_MAX_M || d->P < 1 || d->depth < 0 || d->max_nrhs < 1) return false;
-    if (d->coupling_rows < 0) return false;
+    if (d->coupling_rows < 0 || d->sub_parts < 0) return false;
     if (d->prec != BTD_PREC_F64 && d->prec != BTD_PREC_F32_REFINE) return false;
     if (d->P > 1 && 2 * (int64_t)d->P - 1 > d->N) return false;
     if (d->N > (1 << 24) - 1) return false;
@@ -79,22 +92,56 @@ bool valid_desc(const btd_desc_t* d) {
         }
         if (d->N - 1 - prev < 1) return false;
     }
+    if (d->sub_parts >= 2) {
+        // every subsystem must hold J sub-subsystems: at least 2J - 1 rows
+        std::vector<int> sep;
+        outer_separators(d, sep);
+        for (int k = 0; k < d->P; ++k)
+            if (sep[k + 1] - sep[k] - 1 < 2 * d->sub_parts - 1) return false;
+        if ((int64_t)d->P * d->sub_parts > (1 << 24)) return false;
+    }
     return true;
 }
 
 // Level list and factor-workspace layout for a description.
+// With sub_parts J >= 2: the separators of the level of P*J subsystems
+// (each outer subsystem split equally into J, its J-1 inner separators
+// followed by the outer separator), and of the level above it (P
+// subsystems of J-1 rows, separated at the outer separators' positions).
+void subsystem_levels(const btd_desc_t* d, std::vector<int>& sep0, std::vector<int>& sep1) {
+    const int P = d->P, J = d->sub_parts;
+    std::vector<int> outer, inner;
+    outer_separators(d, outer);
+    sep0.assign(1, -1);
+    for (int k = 0; k < P; ++k) {
+        const int r = outer[k] + 1, nk = outer[k + 1] - outer[k] - 1;
+        equal_split(nk, J, inner);
+        for (int i = 1; i < J; ++i) sep0.push_back(r + inner[i]);
+        sep0.push_back(outer[k + 1]);   // the outer separator (N for the last subsystem)
+    }
+    sep1.assign(P + 1, 0);
+    sep1[0] = -1;
+    for (int k = 0; k < P - 1; ++k) sep1[k + 1] = k * J + J - 1;
+    sep1[P] = P * J - 1;
+}
+
 size_t build_levels(const btd_desc_t* d, std::vector<LevelPlan>& lv) {
     lv.clear();
     size_t off = align_up(sizeof(unsigned long long));  // status word first
-    int N = d->N, P = d->P, depth = d->depth;
+    const int J = d->sub_parts >= 2 ? d->sub_parts : 1;
+    int N = d->N, P = d->P * J, depth = d->depth;
     const int M = d->M;
     const size_t MM = (size_t)M * M;
     const size_t nblk = (size_t)(M + 31) / 32;
-    bool top = true;
+    std::vector<int> sub0, sub1;
+    if (J > 1) subsystem_levels(d, sub0, sub1);
+    int level = 0;
     while (true) {
         LevelPlan L;
         L.N = N; L.M = M; L.P = P;
-        if (top && d->seps && P > 1) {
+        if (J > 1 && level <= 1) {
+            L.sep = level == 0 ? sub0 : sub1;
+        } else if (level == 0 && d->seps && P > 1) {
             L.sep.assign(P + 1, 0);
             L.sep[0] = -1;
             L.sep[P] = N;
@@ -122,11 +169,16 @@ size_t build_levels(const btd_desc_t* d, std::vector<LevelPlan>& lv) {
         lv.push_back(L);
         if (P == 1) break;
         const int Nc = P - 1;
-        const int Pc = (depth > 0) ? coupling_parts(P, M, d->max_nrhs, d->coupling_rows) : 1;
+        int Pc;
+        if (J > 1 && level == 0) {
+            Pc = d->P;   // the level above splits at the outer separators
+        } else {
+            Pc = (depth > 0) ? coupling_parts(P, M, d->max_nrhs, d->coupling_rows) : 1;
+            depth = depth > 0 ? depth - 1 : 0;
+        }
         N = Nc;
         P = Pc;
-        depth = depth > 0 ? depth - 1 : 0;
-        top = false;
+        ++level;
     }
     return off;
 }
@@ -773,7 +825,8 @@ int btd_get_info(btd_plan_t plan, int32_t* status, int32_t* block_row, int32_t* 
 int btd_plan_separators(btd_plan_t plan, int32_t* seps_out) {
     if (!plan || !seps_out) return -1;
     const LevelPlan& L = plan->levels[0];
-    for (int k = 0; k < L.P - 1; ++k) seps_out[k] = L.sep[k + 1];
+    const int J = plan->desc.sub_parts >= 2 ? plan->desc.sub_parts : 1;
+    for (int k = 0; k < plan->desc.P - 1; ++k) seps_out[k] = L.sep[(k + 1) * J];
     return BTD_OK;
 }
 

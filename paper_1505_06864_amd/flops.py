@@ -15,10 +15,31 @@ from . import btd
 CLASSES = btd.KERNEL_CLASSES
 
 
-def levels(N, M, P, depth, max_nrhs, seps=None, coupling_rows=0):
-    """[(N_l, P_l, separators_l)] of every recursion level of a plan."""
+def levels(N, M, P, depth, max_nrhs, seps=None, coupling_rows=0, sub_parts=0):
+    """[(N_l, P_l, separators_l)] of every recursion level of a plan (the
+    rule of btd_factor; with sub_parts J >= 2 the top level has P J
+    subsystems and the next one splits at the P - 1 outer separators)."""
     out = []
-    top = True
+    J = sub_parts if sub_parts >= 2 else 1
+    if J > 1:
+        outer = list(seps) if seps is not None else btd.default_separators(N, P)
+        b = [-1] + outer + [N]
+        s0 = []
+        for k in range(P):
+            r, nk = b[k] + 1, b[k + 1] - b[k] - 1
+            s0 += [r + q for q in btd.default_separators(nk, J)]
+            if k < P - 1:
+                s0.append(b[k + 1])
+        out.append((N, P * J, s0))
+        N = P * J - 1
+        s1 = [k * J + J - 1 for k in range(P - 1)]
+        out.append((N, P, s1))
+        if P == 1:
+            return out
+        Pc = btd.coupling_parts(P, M, max_nrhs, coupling_rows) if depth > 0 else 1
+        N, P, depth = P - 1, Pc, max(depth - 1, 0)
+        seps = None
+    top = J == 1
     while True:
         s = list(seps) if (top and seps is not None) else btd.default_separators(N, P)
         out.append((N, P, s))
@@ -33,7 +54,7 @@ def chunk_sizes(N, P, seps):
     return [b[k + 1] - b[k] - 1 for k in range(P)]
 
 
-def per_class(N, M, R, P, depth=0, max_nrhs=None, seps=None, coupling_rows=0):
+def per_class(N, M, R, P, depth=0, max_nrhs=None, seps=None, coupling_rows=0, sub_parts=0):
     """Dict kernel class -> (total algorithmic FLOPs, number of launch steps).
 
     The launch-step count is that of one stream; when the plan splits a
@@ -45,7 +66,7 @@ def per_class(N, M, R, P, depth=0, max_nrhs=None, seps=None, coupling_rows=0):
     M3, M2R = float(M) ** 3, float(M) ** 2 * R
     tot = {c: 0.0 for c in CLASSES}
     launches = {c: 0 for c in CLASSES}
-    for (Nl, Pl, s) in levels(N, M, P, depth, max_nrhs, seps, coupling_rows):
+    for (Nl, Pl, s) in levels(N, M, P, depth, max_nrhs, seps, coupling_rows, sub_parts):
         nk = chunk_sizes(Nl, Pl, s)
         nmax = max(nk)
         for k, n in enumerate(nk):
@@ -83,9 +104,9 @@ FACTOR_CLASSES = ("fwd_gemm", "getrf", "getrs_factor", "bwd_gemm", "couple")
 SOLVE_CLASSES = ("rhs_sweep", "couple_rhs", "recover")
 
 
-def totals(N, M, R, P, depth=0, max_nrhs=None, seps=None, coupling_rows=0):
+def totals(N, M, R, P, depth=0, max_nrhs=None, seps=None, coupling_rows=0, sub_parts=0):
     """(factor FLOPs, solve FLOPs) of the method (residual excluded)."""
-    pc = per_class(N, M, R, P, depth, max_nrhs, seps, coupling_rows)
+    pc = per_class(N, M, R, P, depth, max_nrhs, seps, coupling_rows, sub_parts)
     return sum(pc[c][0] for c in FACTOR_CLASSES), sum(pc[c][0] for c in SOLVE_CLASSES)
 
 

@@ -116,3 +116,37 @@ def test_coupling_levels_are_the_next_systems():
     for name in ("Hd", "Hb", "Hc"):
         close(l0[name].cpu().numpy(), aux[name], name)
     plan.destroy()
+
+
+@pytest.mark.parametrize("N,M,R,P,J,depth,crow", [(63, 16, 2, 4, 3, 0, 0), (200, 24, 3, 12, 3, 1, 0),
+                                                 (500, 64, 1, 8, 8, 1, 1), (150, 33, 4, 5, 4, 0, 0),
+                                                 (90, 130, 2, 3, 2, 0, 0), (41, 8, 1, 1, 5, 0, 0)])
+def test_subsystem_recursion_matches_oracle(N, M, R, P, J, depth, crow):
+    """Recursion into the subsystems (sub_parts J, Sec. 4.2.2; with depth 1
+    both recursions): the solution element by element against the oracle's
+    literal method (every subsystem solved by the DM with J sub-subsystems),
+    the outer coupling system the library forms (its level 2) against the
+    plain method's coupling blocks, and the outer separators."""
+    torch = require_gpu()
+    print(f"case sub_parts N={N} M={M} R={R} P={P} J={J} depth={depth} coupling_rows={crow}", flush=True)
+    A, B, C, F = inputs.diag_dominant(N, M, R, seed=820 + N)
+    Xo = oracle.dm_solve(A, B, C, F, P, depth=depth, J=J)
+    Ad, Bd, Cd, Fd = to_dev(torch, A, B, C, F)
+    plan = btd.factor(Ad, Bd, Cd, P=P, depth=depth, max_nrhs=R, coupling_rows=crow, sub_parts=J)
+    parts = plan.level_parts()
+    assert parts[0] == P * J and (P == 1 or parts[1] == P), parts
+    X = plan.solve(Fd).cpu().numpy()
+    assert plan.info() == (0, -1, -1)
+    assert_parity(X, Xo, TOL)
+    assert oracle.residual(A, B, C, X, F).max() <= 1e-12
+    if P > 1:
+        assert plan.separators() == oracle.partition(N, P)
+        _, aux = oracle.dm_solve(A, B, C, F, P, depth=0, want_aux=True)
+        out = btd.LevelArrays()
+        assert btd.lib().btd_plan_level_arrays(plan.handle, 2, out) == 0
+        assert (out.N, out.M) == (P - 1, M)
+        l1 = plan.level_arrays(1)
+        for name, ptr in (("Hd", out.A), ("Hb", out.B), ("Hc", out.C)):
+            assert l1[name].data_ptr() == ptr
+            close(l1[name].cpu().numpy(), aux[name], name)
+    plan.destroy()
