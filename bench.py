@@ -42,13 +42,14 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="large", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="large", choices=sorted(WORKLOADS) + ["uneven"])
+    ap.add_argument("--systems", type=int, default=512, help="uneven workload: number of systems")
     ap.add_argument("--P", type=int, default=None)
     ap.add_argument("--depth", type=int, default=None)
     ap.add_argument("--coupling-rows", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--balanced", action="store_true",
-                    help="balanced partition of Sec. 4 (first / last subsystems 7/4 and 7/6 of the others)")
+                    help="balanced partition of Sec. 5.1, Eq. SpeedupMPNk (first / last subsystems 7/4 and 7/6 of the others)")
     ap.add_argument("--no-breakdown", action="store_true",
                     help="skip the factor-only / solve-only timings and the one-subsystem (TA) run")
     ap.add_argument("--cpu-sample-rows", type=int, default=None)
@@ -357,6 +358,137 @@ def sweep(torch, args):
         torch.cuda.empty_cache()
 
 
+def bench_uneven(torch, args):
+    """Batched uneven systems: every system (N ~ U{32..1024}, M in {32, 64,
+    128, 192}, R in {1, 8, 32}) drawn on the device from its own seed; the
+    systems of one M stacked into one system with zero junction blocks and
+    factored + solved by one plan whose parameters the autotuner picks.  One
+    step = every group's factor and solve, one after another on one stream;
+    one JSON line."""
+    import numpy as np
+
+    import oracle
+    from paper_1505_06864_amd import batch, btd, flops, inputs
+    dev = torch.device("cuda:0")
+    specs = inputs.uneven_specs(args.systems)
+    groups = []
+    for M, idx in sorted(batch.group_by_block_size(specs).items()):
+        rows = [specs[s][0] for s in idx]
+        nrhs = [specs[s][2] for s in idx]
+        offsets = np.concatenate([[0], np.cumsum(rows)[:-1]]).astype(int)
+        N = int(sum(rows))
+        A, B, C = (torch.empty((N, M, M), dtype=torch.float64, device=dev) for _ in range(3))
+        Fs = []
+        for s, off, n, r in zip(idx, offsets, rows, nrhs):
+            *_, f = inputs.diag_dominant_device(n, M, r, 3000 + s, device=dev,
+                                                out=(A[off:off + n], B[off:off + n], C[off:off + n]))
+            Fs.append(f)
+            B[off].zero_()
+            C[off + n - 1].zero_()
+        g = batch.Group(M, rows, nrhs, A, B, C, offsets)
+        g.systems = idx
+        F = g.stack_rhs(Fs)
+        del Fs
+        groups.append((g, F))
+    torch.cuda.synchronize()
+    tuner = batch.Tuner()
+    chosen = [tuner.choose(g, F, args.prec) for g, F in groups]
+    fmax = max(btd.workspace_bytes(g.N, g.M, P, d, g.R, None, c)[0] for (g, _), (P, d, c) in zip(groups, chosen))
+    smax = max(btd.workspace_bytes(g.N, g.M, P, d, g.R, None, c)[1] for (g, _), (P, d, c) in zip(groups, chosen))
+    shared = (torch.empty(fmax + 256, dtype=torch.uint8, device=dev), torch.empty(smax + 256, dtype=torch.uint8, device=dev))
+    runs = [batch.GroupRun(g, P, d, c, args.prec, shared=shared) for (g, _), (P, d, c) in zip(groups, chosen)]
+
+    def step():
+        for run, (g, F) in zip(runs, groups):
+            run.step(F)
+            run.release() if args.prec == "f32_refine" else None
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    for run in runs:
+        run.release()
+    # a checked pass: every group's factor status read right after its step
+    # (the groups share one factor workspace and its status word)
+    statuses = []
+    for run, (g, F) in zip(runs, groups):
+        run.step(F)
+        statuses.append(run.info())
+        run.release()
+    Xs = {s: x.clone() for run, (g, _) in zip(runs, groups) for s, x in zip(g.systems, g.split(run.X))}
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = wall * 1e3 / args.steps
+    for run in runs:
+        run.release()
+    fl = sum(sum(flops.totals(g.N, g.M, g.R, P, d, g.R, None, c)) for (g, _), (P, d, c) in zip(groups, chosen))
+    out = {"metric": "batched uneven block-tridiagonal systems solved/s (512 systems, M in {32,64,128,192})",
+           "value": args.systems * args.steps / wall, "unit": "systems/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64" if args.prec == "f64" else "f32 products + f64 refinement", "data": "synthetic",
+           "config": {"workload": f"uneven: {args.systems} systems, N ~ U{{32..1024}}, M in {{32,64,128,192}}, "
+                                  f"R in {{1,8,32}}, diag_dominant_2.0 blocks drawn on the device, "
+                                  + ("FP64" if args.prec == "f64" else "FP32 factor products + FP64 refinement"),
+                      "systems": args.systems, "rows": int(sum(g.N for g, _ in groups))},
+           "tflops": fl / (ms * 1e-3) / 1e12, "frac_fp64_peak": fl / (ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
+           "groups": [{"M": g.M, "systems": len(g.rows), "rows": g.N, "R": g.R, "P": P, "depth": d,
+                       "coupling_rows": c} for (g, _), (P, d, c) in zip(groups, chosen)],
+           "statuses_ok": all(st == (0, -1, -1) for st in statuses),
+           "tuner": tuner.log}
+    if args.prec == "f32_refine":
+        out["refinement"] = {"corrections": sorted({i for r in runs for i in r.iters}),
+                             "final_residual_max": max(x for r in runs for x in r.res)}
+    # sampled parity: the first system of every group against the oracle
+    errs, cpu_s, cpu_fl = [], 0.0, 0.0
+    for g, F in groups:
+        s, off, n = g.systems[0], g.offsets[0], g.rows[0]
+        r = g.nrhs[0]
+        Ah, Bh, Ch = (t[off:off + n].cpu().numpy() for t in (g.A, g.B, g.C))
+        Fh = F[off:off + n, :, :r].cpu().numpy()
+        Ps = max(1, min(16, (n + 1) // 8))
+        t1 = time.perf_counter()
+        Xo = oracle.dm_solve(Ah, Bh, Ch, Fh, Ps, depth=1 if Ps >= 4 else 0)
+        cpu_s += time.perf_counter() - t1
+        cpu_fl += sum(flops.totals(n, g.M, r, Ps, 1 if Ps >= 4 else 0))
+        X = Xs[s].cpu().numpy()
+        d = (X - Xo).reshape(-1, r)
+        errs.append(float(np.max(np.linalg.norm(d, axis=0) / np.linalg.norm(Xo.reshape(-1, r), axis=0))))
+    out["sampled_parity"] = {"systems": [g.systems[0] for g, _ in groups], "max_relerr_vs_oracle": max(errs)}
+    if not args.no_cpu_baseline:
+        model, ncpu = host_cpu()
+        out["cpu_baseline"] = {"value": args.systems / (cpu_s * fl / cpu_fl), "unit": "systems/s",
+                               "cores": oracle.max_threads(), "kind": "oracle", "cpu_model": model,
+                               "sample": f"oracle DM on the first system of each block size ({len(groups)} systems), "
+                                         f"{cpu_s:.2f} s, scaled to the batch by the algorithmic-FLOP ratio "
+                                         f"{fl / cpu_fl:.0f}"}
+    if args.prec == "f64" and not args.no_breakdown:
+        # the whole batch captured once into a HIP graph and replayed
+        s = torch.cuda.Stream(device=dev)
+        s.wait_stream(torch.cuda.current_stream())
+        for run in runs:
+            run.use_stream(s)
+        x_eager = [run.X.clone() for run in runs]
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=s):
+            step()
+        for run in runs:
+            run.X.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            graph.replay()
+        torch.cuda.synchronize()
+        out["graph_ms_per_step"] = (time.perf_counter() - t0) * 1e3 / args.steps
+        out["graph_replay_equals_eager"] = all(bool(torch.equal(run.X, x)) for run, x in zip(runs, x_eager))
+        del graph
+        for run in runs:
+            run.release()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -371,6 +503,9 @@ def main():
         return
     if args.sweep:
         sweep(torch, args)
+        return
+    if args.workload == "uneven":
+        bench_uneven(torch, args)
         return
     from paper_1505_06864_amd import btd, flops
     dev = torch.device("cuda:0")
@@ -450,7 +585,7 @@ def main():
                                + ("FP64" if not mixed else "FP32 factor products + FP64 refinement to 1e-12"),
                    "N": N, "M": M, "R": R, "P": P, "depth": depth, "coupling_rows": crow,
                    "sub_parts": args.sub_parts,
-                   "partition": "balanced (Sec. 4)" if args.balanced else "equal"},
+                   "partition": "balanced (Sec. 5.1, Eq. SpeedupMPNk)" if args.balanced else "equal"},
         "tflops": tflops,
         "frac_fp64_peak": tflops / PEAK_FP64_TFLOPS,
         "gflop_per_solve": (fac + sol) / 1e9,

@@ -80,3 +80,35 @@ def cfg_faddeev(N=2048, M=128, R=4, seed=1):
 
 def cfg_large(R=1, seed=2, N=4096, M=256):
     return diag_dominant(N, M, R, seed, shift=1.5)
+
+
+# Batched uneven systems: (N, M, R) per system drawn with numpy's PCG64 from
+# `seed` (N ~ U{32..1024}, M from {32, 64, 128, 192}, R from {1, 8, 32}),
+# each system drawn with the small workload's recipe (diag_dominant, shift
+# 2) from its own seed 3000 + s.
+def uneven_specs(count=512, seed=3, n_range=(32, 1024), blocks=(32, 64, 128, 192), rhs=(1, 8, 32)):
+    rng = np.random.default_rng(seed)
+    return [(int(rng.integers(n_range[0], n_range[1] + 1)), int(rng.choice(blocks)), int(rng.choice(rhs)))
+            for _ in range(count)]
+
+
+def uneven_system(spec, s):
+    N, M, R = spec
+    return diag_dominant(N, M, R, seed=3000 + s, shift=2.0)
+
+
+def diag_dominant_device(N, M, R, seed, shift=2.0, device="cuda", out=None):
+    """The diag_dominant recipe drawn on the device with torch's generator
+    (a different random stream from the numpy recipe; for inputs too large
+    to draw on the host): A_i = U(-1,1)/(4M) + shift I, B_i, C_i =
+    U(-1,1)/(4M), F ~ N(0, 1).  `out` = optional (A, B, C) tensors to fill."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    s = 1.0 / (4.0 * M)
+    arrs = out or tuple(torch.empty((N, M, M), dtype=torch.float64, device=device) for _ in range(3))
+    for a in arrs:
+        a.uniform_(-s, s, generator=g)
+    arrs[0].diagonal(dim1=1, dim2=2).add_(shift)
+    F = torch.empty((N, M, R), dtype=torch.float64, device=device).normal_(generator=g)
+    return (*arrs, F)
