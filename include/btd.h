@@ -331,7 +331,7 @@ int btd_plan_level_parts(btd_plan_t plan, int32_t level);
  * SuppMatrM rule described for btd_desc_t::depth; 1 = Thomas algorithm).
  * Both return -1 for invalid sizes. */
 int btd_default_separators(int32_t N, int32_t P, int32_t *seps_out);
-/* Host-only: the balanced partition of Sec. 4 (second case of the speedup
+/* Host-only: the balanced partition of Sec. 5.1 (Eq. SpeedupMPNk, second case of the speedup
  * analysis): the first and the last subsystem alpha and beta times as long
  * as the middle ones, whose common size is (N - (P-1)) / (P - 2 + alpha +
  * beta), so that on one processor per subsystem the end subsystems (which

@@ -21,7 +21,7 @@ Functions and the passage each follows:
   partition      equal-split separators (Sec. 2 and Sec. 5).
   balanced_partition
                  first and last subsystems alpha and beta times the middle
-                 ones (Sec. 4, second case of the speedup analysis).
+                 ones (Sec. 5.1, second case of the speedup analysis, Eq. SpeedupMPNk).
   default_m      coupling-system subsystem count (Eq. SuppMatrM).
 """
 import ctypes
@@ -115,7 +115,7 @@ def partition(N, P):
 def balanced_partition(N, P, alpha=7.0 / 4.0, beta=7.0 / 6.0):
     """Separator rows (0-based, length P-1) with subsystem sizes
     n_1 = alpha x, n_P = beta x and x for the others, x = (N - (P-1)) /
-    (P - 2 + alpha + beta) (Sec. 4, second case).  Whole rows: the two end
+    (P - 2 + alpha + beta) (Sec. 5.1, second case, Eq. SpeedupMPNk).  Whole rows: the two end
     sizes rounded to the nearest row (at least one), shortened alternately
     (the longer first) while the middle subsystems would get less than one
     row each; the remaining rows split evenly over the middle subsystems,

@@ -170,7 +170,7 @@ def default_separators(N, P):
 
 
 def balanced_separators(N, P, alpha=7.0 / 4.0, beta=7.0 / 6.0):
-    """Separator rows of the balanced partition (Sec. 4: first and last
+    """Separator rows of the balanced partition (Sec. 5.1, Eq. SpeedupMPNk: first and last
     subsystems alpha and beta times the middle ones), host only."""
     out = (ctypes.c_int32 * max(P - 1, 1))()
     rc = lib().btd_balanced_separators(N, P, ctypes.c_double(alpha), ctypes.c_double(beta), out)

@@ -90,7 +90,7 @@ def test_max_block_size():
 
 @pytest.mark.parametrize("N,M,P,depth", [(200, 24, 8, 0), (301, 40, 12, 1)])
 def test_balanced_partition(N, M, P, depth):
-    """The balanced partition of Sec. 4 (longer first and last subsystems)."""
+    """The balanced partition of Sec. 5.1, Eq. SpeedupMPNk (longer first and last subsystems)."""
     torch = require_gpu()
     A, B, C, F = inputs.diag_dominant(N, M, 2, seed=600 + N)
     check_case(torch, A, B, C, F, P, depth, seps=btd.balanced_separators(N, P))

@@ -238,7 +238,7 @@ def test_partition_rule():
 
 
 def test_balanced_partition_rule():
-    """Sec. 4, second case: end subsystems alpha and beta times the middle
+    """Sec. 5.1, second case (Eq. SpeedupMPNk): end subsystems alpha and beta times the middle
     ones, N_k = (N - (P-1)) / (P - 2 + alpha + beta), in whole rows."""
     for N in range(3, 120, 7):
         for P in range(2, (N + 1) // 2 + 1):
