@@ -60,6 +60,9 @@ def parse():
     ap.add_argument("--prec", choices=("f64", "f32_refine"), default="f64",
                     help="f32_refine: factor products on FP32 MFMA, then iterative refinement to residual 1e-12 "
                          "(FP64 residual, correction and coupling systems); the step is factor + refined solve")
+    ap.add_argument("--schedule", choices=("fused", "separate"), default="fused",
+                    help="fused: one btd_factor_solve call per step (each level's right-hand side on a side "
+                         "stream, overlapped with the factor); separate: btd_factor then btd_solve")
     ap.add_argument("--sub-parts", type=int, default=0,
                     help="recursion into the subsystems: every subsystem solved with J sub-subsystems (Sec. 4.2.2)")
     ap.add_argument("--sweep", choices=("faddeev", "P", "J"), default=None,
@@ -98,7 +101,8 @@ def make_inputs(torch, name, dev):
 class Runner:
     """Direct C-ABI calls with preallocated workspaces (no allocation per step)."""
 
-    def __init__(self, torch, A, B, C, F, P, depth, coupling_rows=0, seps=None, prec="f64", sub_parts=0):
+    def __init__(self, torch, A, B, C, F, P, depth, coupling_rows=0, seps=None, prec="f64", sub_parts=0,
+                 fused=False):
         import ctypes
         from paper_1505_06864_amd import btd
         self.ct, self.btd, self.torch = ctypes, btd, torch
@@ -107,6 +111,7 @@ class Runner:
         self.R = F.shape[2]
         self.A, self.B, self.C, self.F = A, B, C, F
         self.prec = prec
+        self.fused = fused and prec == "f64"
         self.desc, self._keep = btd.make_desc(self.N, self.M, P, depth, self.R, seps, coupling_rows, prec, sub_parts)
         fb, sb = btd.workspace_bytes(self.N, self.M, P, depth, self.R, seps, coupling_rows, sub_parts)
         self.fws, self.fptr = btd._aligned_buffer(fb, A.device)
@@ -144,6 +149,15 @@ class Runner:
     def step(self):
         ct, L = self.ct, self.L
         h = ct.c_void_p()
+        if self.fused:
+            # factor and solve in one call (right-hand sides overlapped with the factor)
+            rc = L.btd_factor_solve(ct.byref(self.desc), self.A.data_ptr(), self.B.data_ptr(), self.C.data_ptr(),
+                                    self.fptr, self.fb, self.R, self.F.data_ptr(), self.X.data_ptr(), self.sptr,
+                                    self.sb, self.sh, ct.byref(h))
+            if rc:
+                raise self.btd.BtdError(rc, "btd_factor_solve")
+            self.plans.append(h)
+            return self.residual()
         rc = L.btd_factor(ct.byref(self.desc), self.A.data_ptr(), self.B.data_ptr(), self.C.data_ptr(),
                           self.fptr, self.fb, self.sh, ct.byref(h))
         if rc:
@@ -167,12 +181,15 @@ class Runner:
         rc = L.btd_solve(h, self.R, self.F.data_ptr(), self.X.data_ptr(), self.sptr, self.sb, self.sh)
         if rc:
             raise self.btd.BtdError(rc, "btd_solve")
-        rc = L.btd_residual(self.N, self.M, self.R, self.A.data_ptr(), self.B.data_ptr(), self.C.data_ptr(),
-                            self.X.data_ptr(), self.F.data_ptr(), self.res.data_ptr(), self.rwork.data_ptr(),
-                            self.sh)
+        self.plans.append(h)
+        self.residual()
+
+    def residual(self):
+        rc = self.L.btd_residual(self.N, self.M, self.R, self.A.data_ptr(), self.B.data_ptr(), self.C.data_ptr(),
+                                 self.X.data_ptr(), self.F.data_ptr(), self.res.data_ptr(), self.rwork.data_ptr(),
+                                 self.sh)
         if rc:
             raise self.btd.BtdError(rc, "btd_residual")
-        self.plans.append(h)
 
     def release(self):
         self.torch.cuda.synchronize()
@@ -200,24 +217,31 @@ def breakdown(torch, run, A, B, C, F, ms_step, reps=5):
     factor_ms = timed(run.factor, reps)
     run.release()
     # the whole step captured once into a HIP graph and replayed: no launch
-    # gaps; every replay must give the eager step's X bit for bit
+    # gaps; every replay must give the eager step's X bit for bit (both
+    # schedules of the FP64 step: one btd_factor_solve call, or btd_factor
+    # then btd_solve)
     run.step()
     torch.cuda.synchronize()
     x_eager = run.X.clone()
     run.release()
     main_stream = run.stream
-    s = torch.cuda.Stream(device=A.device)
-    s.wait_stream(main_stream)
-    graph = torch.cuda.CUDAGraph()
-    run.use_stream(s)
-    with torch.cuda.graph(graph, stream=s):
-        run.step()
-    run.use_stream(main_stream)
-    run.X.zero_()
-    graph_ms = timed(graph.replay, reps)
-    graph_same = bool(torch.equal(run.X, x_eager))
-    del graph
-    run.release()
+    graph_ms, graph_same = {}, True
+    schedule = run.fused
+    for fused in ((schedule, not schedule) if run.prec == "f64" else (schedule,)):
+        run.fused = fused
+        s = torch.cuda.Stream(device=A.device)
+        s.wait_stream(main_stream)
+        graph = torch.cuda.CUDAGraph()
+        run.use_stream(s)
+        with torch.cuda.graph(graph, stream=s):
+            run.step()
+        run.use_stream(main_stream)
+        run.X.zero_()
+        graph_ms["fused" if fused else "separate"] = timed(graph.replay, reps)
+        graph_same = graph_same and bool(torch.equal(run.X, x_eager))
+        del graph
+        run.release()
+    run.fused = schedule
     h = run.factor()
     solve_ms = timed(lambda: run.solve(h), reps)
     run.release()
@@ -229,7 +253,8 @@ def breakdown(torch, run, A, B, C, F, ms_step, reps=5):
     ta_ms = timed(ta.step, 1)
     ta.release()
     ta_flops = sum(flops.totals(N, M, R, 1, 0))
-    return {"factor_ms": factor_ms, "solve_ms": solve_ms, "graph_ms_per_step": graph_ms,
+    return {"factor_ms": factor_ms, "solve_ms": solve_ms, "graph_ms_per_step": graph_ms["fused" if schedule else "separate"],
+            "graph_ms_per_step_by_schedule": graph_ms,
             "graph_replay_equals_eager": graph_same, "ta_one_subsystem_ms": ta_ms,
             "speedup_vs_ta_on_gpu": ta_ms / ms_step,
             "ta_equivalent_tflops": ta_flops / (ms_step * 1e-3) / 1e12,
@@ -346,7 +371,7 @@ def sweep(torch, args):
         name = "large_subsystem_recursion"
     N, M, R = F.shape
     for P, depth, crow, J in configs:
-        run = Runner(torch, A, B, C, F, P, depth, crow, sub_parts=J)
+        run = Runner(torch, A, B, C, F, P, depth, crow, sub_parts=J, fused=args.schedule == "fused")
         ms, resid = time_steps(torch, run, args.steps)
         fl = sum(flops.totals(N, M, R, P, depth, R, None, crow, J))
         print(json.dumps({"sweep": name, "N": N, "M": M, "R": R, "P": P, "sub_parts": J, "depth": depth,
@@ -515,7 +540,7 @@ def main():
     crow = args.coupling_rows if args.coupling_rows is not None else DEFAULT_COUPLING_ROWS
     (A, B, C, F), host = make_inputs(torch, args.workload, dev)
     seps = btd.balanced_separators(N, P) if args.balanced else None
-    run = Runner(torch, A, B, C, F, P, depth, crow, seps, args.prec, args.sub_parts)
+    run = Runner(torch, A, B, C, F, P, depth, crow, seps, args.prec, args.sub_parts, fused=args.schedule == "fused")
     mixed = args.prec == "f32_refine"
 
     for _ in range(args.warmup):
@@ -584,7 +609,7 @@ def main():
         "config": {"workload": f"{args.workload}: {gen} blocks, N={N}, M={M}, R={R}, "
                                + ("FP64" if not mixed else "FP32 factor products + FP64 refinement to 1e-12"),
                    "N": N, "M": M, "R": R, "P": P, "depth": depth, "coupling_rows": crow,
-                   "sub_parts": args.sub_parts,
+                   "sub_parts": args.sub_parts, "schedule": "fused" if run.fused else "separate",
                    "partition": "balanced (Sec. 5.1, Eq. SpeedupMPNk)" if args.balanced else "equal"},
         "tflops": tflops,
         "frac_fp64_peak": tflops / PEAK_FP64_TFLOPS,

@@ -154,6 +154,27 @@ int btd_factor(const btd_desc_t *desc, const double *A, const double *B, const d
                void *factor_ws, size_t factor_bytes, void *stream, btd_plan_t *out);
 
 /*
+ * btd_factor and then btd_solve of nrhs columns (1 <= nrhs <= max_nrhs) in
+ * one call, with the same plan, results and ownership as those two calls.
+ * The difference is the schedule: each recursion level's right-hand-side
+ * sweep and coupling right-hand side (Eqs. e231, e2311) need only that
+ * level's forward-sweep factors, so they run on a library side stream
+ * while the level's spikes (Eq. e232) and the deeper levels are still
+ * being factored; the recoveries (Eq. endSolution) follow on `stream`.
+ * The side stream is forked from and joined back to `stream`, so the call
+ * is ordered on `stream` like any other (and may be captured in a graph).
+ * Without side streams it runs the two steps one after the other.
+ * F, X, solve_ws as for btd_solve (X may equal F); factor_ws and *out as
+ * for btd_factor.
+ * Returns 0; -1..-6 and -8 as btd_factor; -7 nrhs out of range; -9/-10
+ * NULL F/X; -11 NULL or misaligned solve_ws; -12 solve_bytes too small;
+ * BTD_ERR_LAUNCH.  On an error no plan is returned.
+ */
+int btd_factor_solve(const btd_desc_t *desc, const double *A, const double *B, const double *C,
+                     void *factor_ws, size_t factor_bytes, int32_t nrhs, const double *F, double *X,
+                     void *solve_ws, size_t solve_bytes, void *stream, btd_plan_t *out);
+
+/*
  * Solve with a factored plan (Sec. 2, Eqs. e231 (RHS part), e2311 (vector
  * part), e232, endSolution): X = A^{-1} F for nrhs columns,
  * 1 <= nrhs <= max_nrhs.  F and X are [N][M][nrhs]; X may equal F (in

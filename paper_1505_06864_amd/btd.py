@@ -24,7 +24,7 @@ PRECISIONS = {"f64": BTD_PREC_F64, "f32_refine": BTD_PREC_F32_REFINE}
 BTD_MAX_M = 512
 
 # Every symbol include/btd.h declares.
-EXPORTS = ("btd_workspace_bytes", "btd_factor", "btd_solve", "btd_solve_batch", "btd_solve_noalloc", "btd_refine_work_bytes", "btd_solve_refine", "btd_solve_local",
+EXPORTS = ("btd_workspace_bytes", "btd_factor", "btd_factor_solve", "btd_solve", "btd_solve_batch", "btd_solve_noalloc", "btd_refine_work_bytes", "btd_solve_refine", "btd_solve_local",
            "btd_solve_finish", "btd_get_solve_info", "btd_plan_level_arrays", "btd_residual_work_bytes",
            "btd_residual", "btd_get_info", "btd_plan_separators", "btd_plan_level_parts",
            "btd_default_separators", "btd_balanced_separators", "btd_default_coupling_parts",
@@ -61,6 +61,8 @@ def lib():
         vp, sz, i32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32
         L.btd_workspace_bytes.argtypes = [ctypes.POINTER(Desc), ctypes.POINTER(sz), ctypes.POINTER(sz)]
         L.btd_factor.argtypes = [ctypes.POINTER(Desc), vp, vp, vp, vp, sz, vp, ctypes.POINTER(vp)]
+        L.btd_factor_solve.argtypes = [ctypes.POINTER(Desc), vp, vp, vp, vp, sz, i32, vp, vp, vp, sz, vp,
+                                       ctypes.POINTER(vp)]
         L.btd_solve.argtypes = [vp, i32, vp, vp, vp, sz, vp]
         L.btd_solve_batch.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(i32), ctypes.POINTER(vp),
                                       ctypes.POINTER(vp), vp, sz, vp]
@@ -196,10 +198,14 @@ def coupling_parts(P, M, R, coupling_rows=0):
 
 
 class Plan:
-    """A factored system (btd_factor).  Keeps A, B, C and the factor workspace alive."""
+    """A factored system (btd_factor).  Keeps A, B, C and the factor workspace alive.
+
+    With F given the plan is built by btd_factor_solve, which also solves
+    for F in the same call (into X, or a new array); the solution is
+    ``self.X``."""
 
     def __init__(self, A, B, C, P=1, depth=0, max_nrhs=1, seps=None, stream=None, coupling_rows=0, prec="f64",
-                 sub_parts=0):
+                 sub_parts=0, F=None, X=None):
         N, M = A.shape[0], A.shape[1]
         for t, n in ((A, "A"), (B, "B"), (C, "C")):
             _check(t, n, (N, M, M))
@@ -210,10 +216,26 @@ class Plan:
         self._ws, ptr = _aligned_buffer(fbytes, A.device, stream)
         d, _keep = make_desc(N, M, P, depth, max_nrhs, seps, coupling_rows, prec, sub_parts)
         h = ctypes.c_void_p()
-        rc = lib().btd_factor(ctypes.byref(d), A.data_ptr(), B.data_ptr(), C.data_ptr(), ptr, fbytes,
-                              _stream_handle(stream, A.device), ctypes.byref(h))
-        if rc != BTD_OK:
-            raise BtdError(rc, "btd_factor")
+        self.X = None
+        if F is None:
+            rc = lib().btd_factor(ctypes.byref(d), A.data_ptr(), B.data_ptr(), C.data_ptr(), ptr, fbytes,
+                                  _stream_handle(stream, A.device), ctypes.byref(h))
+            if rc != BTD_OK:
+                raise BtdError(rc, "btd_factor")
+        else:
+            R = F.shape[2]
+            _check(F, "F", (N, M, R))
+            if X is None:
+                X = _empty_on(stream, F.shape, dtype=F.dtype, device=F.device)
+            _check(X, "X", (N, M, R))
+            buf, sptr = _aligned_buffer(self.solve_bytes, F.device, stream)
+            rc = lib().btd_factor_solve(ctypes.byref(d), A.data_ptr(), B.data_ptr(), C.data_ptr(), ptr, fbytes, R,
+                                        F.data_ptr(), X.data_ptr(), sptr, self.solve_bytes,
+                                        _stream_handle(stream, A.device), ctypes.byref(h))
+            if rc != BTD_OK:
+                raise BtdError(rc, "btd_factor_solve")
+            self._last_solve_ws = buf
+            self.X = X
         self._h = h
         self.factor_bytes = fbytes
 
@@ -377,6 +399,14 @@ class Plan:
 def factor(A, B, C, P=1, depth=0, max_nrhs=1, seps=None, stream=None, coupling_rows=0, prec="f64", sub_parts=0):
     return Plan(A, B, C, P=P, depth=depth, max_nrhs=max_nrhs, seps=seps, stream=stream, coupling_rows=coupling_rows,
                 prec=prec, sub_parts=sub_parts)
+
+
+def factor_solve(A, B, C, F, X=None, P=1, depth=0, max_nrhs=None, seps=None, stream=None, coupling_rows=0,
+                 prec="f64", sub_parts=0):
+    """btd_factor_solve: factor and solve for F in one call.  Returns (plan, X)."""
+    p = Plan(A, B, C, P=P, depth=depth, max_nrhs=max_nrhs or F.shape[2], seps=seps, stream=stream,
+             coupling_rows=coupling_rows, prec=prec, sub_parts=sub_parts, F=F, X=X)
+    return p, p.X
 
 
 def solve_batch(plans, Fs, Xs=None, stream=None, lanes=1):

@@ -209,7 +209,7 @@ std::mutex g_side_mu;
 
 struct ThreadEvents {
     bool ready = false;
-    hipEvent_t fork = nullptr, join[kMaxGroups] = {};
+    hipEvent_t fork = nullptr, join[kMaxGroups] = {}, aux[kMaxGroups + 1] = {};
 };
 thread_local ThreadEvents t_events[kMaxDevices];
 
@@ -217,6 +217,7 @@ struct StreamPool {
     hipStream_t* s;
     hipEvent_t fork;
     hipEvent_t* join;
+    hipEvent_t* aux;   // kMaxGroups + 1 more events of the calling thread
 };
 
 // Side streams of the current device and the calling thread's events; false
@@ -239,11 +240,14 @@ bool stream_pool(StreamPool& out) {
         if (!ev.fork && hipEventCreateWithFlags(&ev.fork, hipEventDisableTiming) != hipSuccess) return false;
         for (int g = 0; g < kMaxGroups; ++g)
             if (!ev.join[g] && hipEventCreateWithFlags(&ev.join[g], hipEventDisableTiming) != hipSuccess) return false;
+        for (int g = 0; g <= kMaxGroups; ++g)
+            if (!ev.aux[g] && hipEventCreateWithFlags(&ev.aux[g], hipEventDisableTiming) != hipSuccess) return false;
         ev.ready = true;
     }
     out.s = side.s;
     out.fork = ev.fork;
     out.join = ev.join;
+    out.aux = ev.aux;
     return true;
 }
 
@@ -373,7 +377,74 @@ namespace {
         if (e_ != hipSuccess) return BTD_ERR_LAUNCH;   \
     } while (0)
 
-int enqueue_factor(btd_plan_s* p, hipStream_t s) {
+// A solve enqueued together with the factor: every level's right-hand-side
+// sweep and coupling right-hand side run on their own stream `rs` as soon as
+// that level's forward sweep (the LU factors and E) is done, so they overlap
+// the level's backward sweep and the factorisation of the deeper levels;
+// the recoveries follow on the caller's stream once the whole factor and
+// the deepest level's solve are done.
+struct FusedSolve {
+    int R;
+    const double* F;
+    double* X;
+    char* sws;
+    hipStream_t rs;
+    hipEvent_t* fw;      // per chunk group: forward sweep done (the calling thread's events)
+    hipEvent_t done;     // the right-hand-side stream's last sweep
+};
+
+int enqueue_sweep(const btd_plan_s* p, size_t l, int R, const double* F, double* X, hipStream_t s);
+int enqueue_couple_rhs(const btd_plan_s* p, size_t l, int R, const double* F, double* X, double* Fc,
+                       hipStream_t s, bool recover);
+int enqueue_rhs_check(const btd_plan_s* p, int R, const double* F, hipStream_t s);
+int enqueue_solve_level(const btd_plan_s* p, size_t l, int R, const double* F, double* X, char* sws,
+                        size_t sws_off, hipStream_t s);
+int enqueue_factor(btd_plan_s* p, hipStream_t s, FusedSolve* fs = nullptr);
+
+// Offset in the solve workspace of level l's coupling right-hand side (the
+// layout enqueue_solve_level walks: one block per level with P > 1).
+size_t level_fc_offset(const btd_plan_s* p, size_t l, int R) {
+    size_t off = 0;
+    for (size_t k = 0; k < l; ++k) {
+        const LevelPlan& L = p->levels[k];
+        if (L.P > 1) off = align_up(off + sizeof(double) * (size_t)(L.P - 1) * L.M * R);
+    }
+    return off;
+}
+
+// Factor and solve in one launch sequence (FusedSolve); without side streams
+// the factor and then the solve on the caller's stream.
+int enqueue_factor_solve(btd_plan_s* p, int R, const double* F, double* X, char* sws, hipStream_t s) {
+    StreamPool pool{};
+    if (!stream_pool(pool)) {
+        int rc = enqueue_factor(p, s);
+        if (rc != BTD_OK) return rc;
+        rc = enqueue_rhs_check(p, R, F, s);
+        if (rc != BTD_OK) return rc;
+        return enqueue_solve_level(p, 0, R, F, X, sws, 0, s);
+    }
+    FusedSolve fs{R, F, X, sws, pool.s[kMaxGroups - 1], pool.aux, pool.aux[kMaxGroups]};
+    // the right-hand-side stream starts after the caller's earlier work
+    BTD_TRY(hipEventRecord(pool.fork, s));
+    BTD_TRY(hipStreamWaitEvent(fs.rs, pool.fork, 0));
+    int rc = enqueue_rhs_check(p, R, F, fs.rs);
+    if (rc != BTD_OK) return rc;
+    rc = enqueue_factor(p, s, &fs);
+    if (rc != BTD_OK) return rc;
+    BTD_TRY(hipEventRecord(fs.done, fs.rs));
+    BTD_TRY(hipStreamWaitEvent(s, fs.done, 0));
+    // recoveries, deepest level first, on the caller's stream
+    for (size_t l = p->levels.size(); l-- > 0;) {
+        if (p->levels[l].P == 1) continue;
+        const double* Fl = l == 0 ? F : (const double*)(sws + level_fc_offset(p, l - 1, R));
+        double* Xl = l == 0 ? X : (double*)(sws + level_fc_offset(p, l - 1, R));
+        rc = enqueue_couple_rhs(p, l, R, Fl, Xl, (double*)(sws + level_fc_offset(p, l, R)), s, true);
+        if (rc != BTD_OK) return rc;
+    }
+    return BTD_OK;
+}
+
+int enqueue_factor(btd_plan_s* p, hipStream_t s, FusedSolve* fs) {
     BTD_TRY(btd::launch_init_status(p->status, s));
     for (size_t l = 0; l < p->levels.size(); ++l) {
         const LevelPlan& LP = p->levels[l];
@@ -385,8 +456,9 @@ int enqueue_factor(btd_plan_s* p, hipStream_t s) {
         ka.nc = LP.P;
         ka.lowp = (p->desc.prec == BTD_PREC_F32_REFINE && l == 0) ? 1 : 0;
         BTD_TRY(btd::launch_write_ints((int*)(p->ws + LP.off_sep), LP.sep.data(), LP.P + 1, s));
-        // chunk groups, each on its own stream (one group: the caller's stream)
-        int G = chunk_groups(LP.P);
+        // chunk groups, each on its own stream (one group: the caller's stream);
+        // with a fused solve the last side stream belongs to the right-hand side
+        int G = std::min(chunk_groups(LP.P), fs ? kMaxGroups - 1 : kMaxGroups);
         StreamPool pool{};
         if (G > 1 && !stream_pool(pool)) G = 1;
         hipStream_t gs[kMaxGroups];
@@ -408,6 +480,22 @@ int enqueue_factor(btd_plan_s* p, hipStream_t s) {
                 BTD_TRY(timed(BTD_KC_GETRF, gs[g], btd::launch_getrf, gk[g]));
                 BTD_TRY(timed(BTD_KC_DIAG_PREP, gs[g], btd::launch_diag_inv, gk[g]));
                 BTD_TRY(timed(BTD_KC_GETRS_FACTOR, gs[g], btd::launch_getrs, gk[g]));
+            }
+        }
+        if (fs) {
+            // this level's right-hand side needs its forward-sweep factors only
+            for (int g = 0; g < G; ++g) {
+                BTD_TRY(hipEventRecord(fs->fw[g], gs[g]));
+                BTD_TRY(hipStreamWaitEvent(fs->rs, fs->fw[g], 0));
+            }
+            const double* Fl = l == 0 ? fs->F : (const double*)(fs->sws + level_fc_offset(p, l - 1, fs->R));
+            double* Xl = l == 0 ? fs->X : (double*)(fs->sws + level_fc_offset(p, l - 1, fs->R));
+            int rc = enqueue_sweep(p, l, fs->R, Fl, Xl, fs->rs);
+            if (rc != BTD_OK) return rc;
+            if (LP.P > 1) {
+                rc = enqueue_couple_rhs(p, l, fs->R, Fl, Xl, (double*)(fs->sws + level_fc_offset(p, l, fs->R)), fs->rs,
+                                        false);
+                if (rc != BTD_OK) return rc;
             }
         }
         if (LP.P > 1) {
@@ -548,8 +636,13 @@ int btd_workspace_bytes(const btd_desc_t* desc, size_t* factor_ws, size_t* solve
     return BTD_OK;
 }
 
-int btd_factor(const btd_desc_t* desc, const double* A, const double* B, const double* C, void* factor_ws,
-               size_t factor_bytes, void* stream, btd_plan_t* out) {
+}  // extern "C"
+
+namespace {
+
+// Checks btd_factor's arguments and builds the host plan (nothing enqueued).
+int new_plan(const btd_desc_t* desc, const double* A, const double* B, const double* C, void* factor_ws,
+             size_t factor_bytes, btd_plan_t* out, btd_plan_s** plan) {
     if (!valid_desc(desc)) return -1;
     if (!A) return -2;
     if (!B) return -3;
@@ -572,7 +665,37 @@ int btd_factor(const btd_desc_t* desc, const double* A, const double* B, const d
     p->A = A; p->B = B; p->C = C;
     p->status = (unsigned long long*)((char*)factor_ws + kFactorStatus);
     p->solve_status = (unsigned long long*)((char*)factor_ws + kSolveStatus);
+    *plan = p;
+    return BTD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int btd_factor(const btd_desc_t* desc, const double* A, const double* B, const double* C, void* factor_ws,
+               size_t factor_bytes, void* stream, btd_plan_t* out) {
+    btd_plan_s* p = nullptr;
+    int rc = new_plan(desc, A, B, C, factor_ws, factor_bytes, out, &p);
+    if (rc != BTD_OK) return rc;
     rc = enqueue_factor(p, (hipStream_t)stream);
+    if (rc != BTD_OK) { delete p; return rc; }
+    *out = p;
+    return BTD_OK;
+}
+
+int btd_factor_solve(const btd_desc_t* desc, const double* A, const double* B, const double* C, void* factor_ws,
+                     size_t factor_bytes, int32_t nrhs, const double* F, double* X, void* solve_ws,
+                     size_t solve_bytes, void* stream, btd_plan_t* out) {
+    if (desc && valid_desc(desc) && (nrhs < 1 || nrhs > desc->max_nrhs)) return -7;
+    if (!F) return -9;
+    if (!X) return -10;
+    btd_plan_s* p = nullptr;
+    int rc = new_plan(desc, A, B, C, factor_ws, factor_bytes, out, &p);
+    if (rc != BTD_OK) return rc;
+    if (!solve_ws || ((uintptr_t)solve_ws % kAlign) != 0) { delete p; return -11; }
+    if (solve_bytes < solve_bytes_for(p->levels, nrhs)) { delete p; return -12; }
+    rc = enqueue_factor_solve(p, nrhs, F, X, (char*)solve_ws, (hipStream_t)stream);
     if (rc != BTD_OK) { delete p; return rc; }
     *out = p;
     return BTD_OK;

@@ -66,6 +66,21 @@ def test_factor_rejects_bad_arguments_before_device_work():
     assert L.btd_factor(ctypes.byref(d), fake, fake, fake, fake, 16, None, ctypes.byref(h)) == -6
     assert L.btd_factor(ctypes.byref(d), fake, fake, fake, fake, 1 << 20, None, None) == -8
     assert L.btd_solve(None, 1, fake, fake, fake, 1 << 20, None) == -1
+    fs = L.btd_factor_solve
+    assert fs(None, fake, fake, fake, fake, 1 << 20, 1, fake, fake, fake, 1 << 20, None, ctypes.byref(h)) == -1
+    assert fs(ctypes.byref(d), fake, fake, fake, fake, 1 << 20, 0, fake, fake, fake, 1 << 20, None,
+              ctypes.byref(h)) == -7
+    assert fs(ctypes.byref(d), fake, fake, fake, fake, 1 << 20, 2, fake, fake, fake, 1 << 20, None,
+              ctypes.byref(h)) == -7
+    assert fs(ctypes.byref(d), fake, fake, fake, fake, 1 << 20, 1, None, fake, fake, 1 << 20, None,
+              ctypes.byref(h)) == -9
+    assert fs(ctypes.byref(d), fake, fake, fake, fake, 1 << 20, 1, fake, None, fake, 1 << 20, None,
+              ctypes.byref(h)) == -10
+    assert fs(ctypes.byref(d), None, fake, fake, fake, 1 << 20, 1, fake, fake, fake, 1 << 20, None,
+              ctypes.byref(h)) == -2
+    assert fs(ctypes.byref(d), fake, fake, fake, fake, 16, 1, fake, fake, fake, 1 << 20, None,
+              ctypes.byref(h)) == -6
+    assert fs(ctypes.byref(d), fake, fake, fake, fake, 1 << 20, 1, fake, fake, fake, 1 << 20, None, None) == -8
     assert L.btd_solve_batch(-1, None, None, None, None, None, 0, None) == -1
     assert L.btd_solve_batch(0, None, None, None, None, None, 0, None) == 0
     assert L.btd_residual(0, 4, 1, fake, fake, fake, fake, fake, fake, fake, None) == -1

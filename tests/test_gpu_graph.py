@@ -21,8 +21,8 @@ pytestmark = pytest.mark.gpu
 class AbiRun:
     """factor + solve through the C ABI with workspaces allocated once."""
 
-    def __init__(self, torch, A, B, C, F, P, depth):
-        self.torch, self.L = torch, btd.lib()
+    def __init__(self, torch, A, B, C, F, P, depth, fused=False):
+        self.torch, self.L, self.fused = torch, btd.lib(), fused
         self.A, self.B, self.C, self.F = to_dev(torch, A, B, C, F)
         N, M, R = F.shape
         self.R = R
@@ -36,6 +36,13 @@ class AbiRun:
     def enqueue(self, stream):
         sh = ctypes.c_void_p(stream.cuda_stream)
         h = ctypes.c_void_p()
+        if self.fused:
+            rc = self.L.btd_factor_solve(ctypes.byref(self.desc), self.A.data_ptr(), self.B.data_ptr(),
+                                         self.C.data_ptr(), self.fptr, self.fb, self.R, self.F.data_ptr(),
+                                         self.X.data_ptr(), self.sptr, self.sb, sh, ctypes.byref(h))
+            assert rc == 0, rc
+            self.plans.append(h)
+            return h
         rc = self.L.btd_factor(ctypes.byref(self.desc), self.A.data_ptr(), self.B.data_ptr(), self.C.data_ptr(),
                                self.fptr, self.fb, sh, ctypes.byref(h))
         assert rc == 0, rc
@@ -51,13 +58,16 @@ class AbiRun:
         self.plans = []
 
 
-@pytest.mark.parametrize("N,M,R,P,depth", [(80, 16, 2, 16, 1), (40, 33, 3, 6, 0)])
-def test_graph_replay_matches_eager(N, M, R, P, depth):
+@pytest.mark.parametrize("N,M,R,P,depth,fused", [(80, 16, 2, 16, 1, False), (40, 33, 3, 6, 0, False),
+                                                   (80, 16, 2, 16, 1, True), (200, 32, 3, 40, 2, True)])
+def test_graph_replay_matches_eager(N, M, R, P, depth, fused):
+    """fused: the graph holds one btd_factor_solve call (its right-hand-side
+    side stream is part of the captured fork and join)."""
     torch = require_gpu()
-    print(f"case graph N={N} M={M} R={R} P={P} depth={depth}", flush=True)
+    print(f"case graph N={N} M={M} R={R} P={P} depth={depth} fused={fused}", flush=True)
     A, B, C, F = inputs.diag_dominant(N, M, R, seed=700 + N)
     A2, B2, C2, F2 = inputs.diag_dominant(N, M, R, seed=900 + N)
-    run, other = AbiRun(torch, A, B, C, F, P, depth), AbiRun(torch, A2, B2, C2, F2, P, depth)
+    run, other = AbiRun(torch, A, B, C, F, P, depth, fused), AbiRun(torch, A2, B2, C2, F2, P, depth)
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(s):
