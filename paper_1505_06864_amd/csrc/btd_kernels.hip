@@ -304,7 +304,10 @@ __device__ bool make_job(const KArgs& ka, int b, int part, Job& j) {
 // LDS: two buffers of As[16][64+AP] (k-major, transposed) and Bs[16][64+BP];
 // the next K step is loaded (32-byte pieces when the rows are 32-byte
 // aligned) while the current one is multiplied, one barrier per K step.
-constexpr int TB = 64, KB = 16, AP = 4, BP = 4;
+// AP = 3: the transposed stores of As (lanes 4 k-rows apart writing the
+// same tile row) then fall in different LDS banks (with a pad of 4 they
+// collided four ways).
+constexpr int TB = 64, KB = 16, AP = 3, BP = 4;
 constexpr int ASZ = KB * (TB + AP), BSZ = KB * (TB + BP);
 
 template <bool FULL>
@@ -1035,6 +1038,283 @@ __device__ __forceinline__ void lw_panel_steps(double (&v)[4][LW_NB], bool (&act
     }
 }
 
+// ------------------------------------------------------------------ LU, no interchanges
+//
+// Partial pivoting chooses the diagonal entry as the pivot of column c
+// exactly when no entry below it is larger in magnitude, i.e. when every
+// multiplier of the column satisfies |l| <= 1.  For block diagonally
+// dominant systems this holds at every column, and the factorisation is
+// then an LU without row interchanges, which needs no pivot search: the
+// M x M block (M a multiple of 32, at most 256) is factored right-looking
+// in 32-column panels:
+//   D  one wave factors the 32 x 32 diagonal block A11 (one row per lane,
+//      the pivot row broadcast through LDS) and inverts L11 and U11
+//      (lanes 0-31 one column of inv(L11) each, lanes 32-63 one column of
+//      inv(U11), as forward substitutions);
+//   P  L21 = A21 inv(U11) and U12 = inv(L11) A12 on MFMA (all waves);
+//   U  A22 -= L21 U12 on MFMA, two 16 x 16 tiles per wave at a time.
+// Every pivot is checked to be finite and non-zero and every multiplier
+// to satisfy |l| <= 1; if any check fails the factorisation is abandoned
+// and the block is factored with interchanges from its unchanged working
+// copy (the fast path reads the working copy and writes only the factor
+// array).  On success the factors are those of partial pivoting with the
+// identity permutation.
+constexpr int NP_NB = 32, NP_TP = 33, NP_LPP = 33, NP_UPP = 228;
+
+struct NpLds {
+    size_t t11, f11, il, iu, ds, lp, up, flag, total;
+};
+
+// t11: the factored diagonal block, f11 the same block flipped; il, iu:
+// inv(L11), inv(U11); ds: 32 ones, the reciprocals of the diagonal of U11
+// in reverse order, then in order (published during the factorisation); lp: L21 (rows below the block x 32);
+// up: U12 (32 x columns right of the block); flag: failure of a check.
+__host__ __device__ constexpr NpLds np_lds_layout() {
+    NpLds l{};
+    size_t off = 0;
+    l.t11 = off; off += sizeof(double) * NP_NB * NP_TP;
+    l.il = off; off += sizeof(double) * NP_NB * NP_TP;
+    l.iu = off; off += sizeof(double) * NP_NB * NP_TP;
+    l.ds = off; off += sizeof(double) * 3 * NP_NB;
+    l.lp = off; off += sizeof(double) * (256 - NP_NB) * NP_LPP;
+    l.f11 = l.lp;   // F is needed only before L21 is formed
+    l.up = off; off += sizeof(double) * NP_NB * NP_UPP;
+    l.flag = off; off += 16;
+    l.total = off;
+    return l;
+}
+static_assert(np_lds_layout().total <= lw_lds_layout().total, "no-interchange LU must fit the LU's LDS");
+
+// Phase D on one wave: factor A11 (rows j0.. of src, columns j0..) into T and
+// out, inverses into IL and IU.  Returns this lane's checks.
+__device__ __forceinline__ bool np_diag(const double* __restrict__ src, double* __restrict__ out, int M, int j0,
+                                        double* T, double* F, double* IL, double* IU, double* DS, int lane) {
+    constexpr int TP = NP_TP;
+    const bool rowl = lane < 32;
+    const int r = lane & 31;
+    double v[32];
+    const double* srow = src + (size_t)(j0 + r) * M + j0;
+#pragma unroll
+    for (int c = 0; c < 32; c += 2) {
+        const double2 x = *(const double2*)(srow + c);
+        v[c] = x.x;
+        v[c + 1] = x.y;
+    }
+    bool ok = true;
+    double* RP = DS + 64;   // reciprocal of each pivot, published with its row
+#pragma unroll
+    for (int c = 0; c < 32; ++c) {
+        // the lane index made opaque per step: the step's lane masks are
+        // formed here, not all 64 of them up front (scalar register pressure)
+        int ln = lane;
+        __asm__ volatile("" : "+v"(ln));
+        // row c is final: its lane publishes it from c on, with 1 / pivot
+        if (ln == c) {
+            double rc = __builtin_amdgcn_rcp(v[c]);
+            rc = fma(rc, fma(-v[c], rc, 1.0), rc);
+            rc = fma(rc, fma(-v[c], rc, 1.0), rc);
+            RP[c] = rc;
+#pragma unroll
+            for (int q = 0; q < 32; ++q)
+                if (q >= c) T[c * TP + q] = v[q];
+        }
+        wave_lds_sync();
+        const double pv = T[c * TP + c];
+        const double rp = RP[c];
+        ok = ok && pv != 0.0 && isfinite(pv);
+        const bool act = ln < 32 && (ln & 31) > c;
+        const double l = v[c] * rp;
+        ok = ok && (!act || fabs(l) <= 1.0);
+        // no branch: the rows above get a zero multiple (a non-finite pivot
+        // row fails the checks later on) and keep their U part in T, so
+        // their v[c] is never read again
+        const double le = act ? l : 0.0;
+        v[c] = l;
+#pragma unroll
+        for (int q = 0; q < 32; ++q)
+            if (q > c) v[q] = fma(-le, T[c * TP + q], v[q]);
+    }
+    // the factored rows: the multipliers left of the diagonal join the U
+    // parts already in T; then the rows to out, and the block flipped,
+    // F[a][b] = T[31-a][31-b], whose lower triangle is U11 reversed
+    if (rowl) {
+#pragma unroll
+        for (int q = 0; q < 32; ++q)
+            if (q < r) T[r * TP + q] = v[q];
+    }
+    wave_lds_sync();
+    if (rowl) {
+        double* orow = out + (size_t)(j0 + r) * M + j0;
+#pragma unroll
+        for (int q = 0; q < 32; q += 2) {
+            const double t0 = T[r * TP + q], t1 = T[r * TP + q + 1];
+            *(double2*)(orow + q) = make_double2(t0, t1);
+            F[(31 - r) * TP + 31 - q] = t0;
+            F[(31 - r) * TP + 30 - q] = t1;
+        }
+    }
+    wave_lds_sync();
+    if (rowl) {
+        DS[32 + 31 - r] = 1.0 / T[r * TP + r];
+        DS[r] = 1.0;
+    }
+    wave_lds_sync();
+    // inverses by forward substitution with a lower triangle: lanes 0-31
+    // column j of inv(L11) (unit diagonal, the lower triangle of T); lanes
+    // 32-63 column 31-j of inv(U') for U' the lower triangle of F, whose
+    // inverse is inv(U11) reversed: inv(U11)[31-a][j] = inv(U')[a][31-j]
+    const bool up = !rowl;
+    const int jt = up ? 31 - r : r;
+    const double* Mh = up ? F : T;
+    const double* Dh = DS + (up ? 32 : 0);
+    double x[32];
+#pragma unroll
+    for (int a = 0; a < 32; ++a) {
+        // four partial sums: a short dependent chain per row (the unit
+        // column's index opaque per row: no 32 masks formed up front)
+        int jo = jt;
+        __asm__ volatile("" : "+v"(jo));
+        double s4[4] = {a == jo ? 1.0 : 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int b = 0; b < 32; ++b)
+            if (b < a) s4[b & 3] = fma(-Mh[a * TP + b], x[b], s4[b & 3]);
+        x[a] = ((s4[0] + s4[1]) + (s4[2] + s4[3])) * Dh[a];
+    }
+#pragma unroll
+    for (int a = 0; a < 32; ++a) {
+        double* d = up ? IU + (31 - a) * TP + r : IL + a * TP + r;   // no branch: keeps x in registers
+        *d = x[a];
+    }
+    return ok;
+}
+
+// The no-interchange factorisation of one block; false (nothing but out
+// written) when a check fails.  Called by all threads of the LU workgroup.
+__device__ __forceinline__ bool getrf_nointerchange(const double* __restrict__ a, double* __restrict__ out, int* __restrict__ perm,
+                                    int M, char* smc) {
+    constexpr NpLds lay = np_lds_layout();
+    constexpr int TP = NP_TP, LPP = NP_LPP, UPP = NP_UPP;
+    // array offsets kept in registers: every LDS access is then a register
+    // base plus an immediate, instead of one scalar address constant per
+    // access of the unrolled code (scalar register pressure)
+    int off[7] = {(int)(lay.t11 / 8), (int)(lay.f11 / 8), (int)(lay.il / 8), (int)(lay.iu / 8),
+                  (int)(lay.ds / 8), (int)(lay.lp / 8), (int)(lay.up / 8)};
+#pragma unroll
+    for (int k = 0; k < 7; ++k) __asm__ volatile("" : "+v"(off[k]));
+    double* sd = (double*)smc;
+    double* T = sd + off[0];
+    double* F = sd + off[1];
+    double* IL = sd + off[2];
+    double* IU = sd + off[3];
+    double* DS = sd + off[4];
+    double* LP = sd + off[5];
+    double* UP = sd + off[6];
+    int* FL = (int*)(smc + lay.flag);
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    constexpr int NW = LW_NT / 64;
+    if (tid == 0) FL[0] = 0;
+    __syncthreads();
+    for (int j0 = 0; j0 < M; j0 += NP_NB) {
+        // per-lane offsets made opaque per panel, so that the products' lane
+        // addresses are not hoisted out of the loop and kept live across the
+        // diagonal block (register pressure)
+        int lv = lane;
+        __asm__ volatile("" : "+v"(lv));
+        const int g = lv >> 4, cc = lv & 15;
+        const double* src = j0 == 0 ? a : out;   // the trailing matrix: the working copy, then out
+        const int m2 = M - j0 - NP_NB;            // rows below = columns right of the block
+        if (w == 0) {
+            const bool ok = np_diag(src, out, M, j0, T, F, IL, IU, DS, lane);
+            if (__ballot(!ok) != 0ull && lane == 0) FL[0] = 1;
+        }
+        __syncthreads();
+        if (FL[0]) return false;
+        if (m2 == 0) break;
+        const int nt2 = m2 / 16;
+        // ---- P: L21 = A21 inv(U11) by 16-row blocks (tasks q < nt2) and
+        // U12 = inv(L11) A12 by 16-column blocks; a task reads all 32 columns
+        // (rows) of its block before it overwrites them (in place from the
+        // second panel on), so no two tasks share a block
+        bool okp = true;
+        for (int q = w; q < 2 * nt2; q += NW) {
+            v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+            if (q < nt2) {
+                const double* arow = src + (size_t)(j0 + NP_NB + 16 * q + cc) * M + j0 + g;
+                double av[8];
+#pragma unroll
+                for (int kk = 0; kk < 8; ++kk) av[kk] = arow[4 * kk];
+#pragma unroll
+                for (int kk = 0; kk < 8; ++kk) {
+                    acc0 = mfma4(av[kk], IU[(4 * kk + g) * TP + cc], acc0);
+                    acc1 = mfma4(av[kk], IU[(4 * kk + g) * TP + 16 + cc], acc1);
+                }
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = 16 * q + g + 4 * v;
+                    okp = okp && fabs(acc0[v]) <= 1.0 && fabs(acc1[v]) <= 1.0;
+                    double* orow = out + (size_t)(j0 + NP_NB + row) * M + j0;
+                    orow[cc] = acc0[v];
+                    orow[16 + cc] = acc1[v];
+                    LP[row * LPP + cc] = acc0[v];
+                    LP[row * LPP + 16 + cc] = acc1[v];
+                }
+            } else {
+                const int u = q - nt2;
+                const double* bcol = src + (size_t)(j0 + g) * M + j0 + NP_NB + 16 * u + cc;
+                double bv[8];
+#pragma unroll
+                for (int kk = 0; kk < 8; ++kk) bv[kk] = bcol[(size_t)4 * kk * M];
+#pragma unroll
+                for (int kk = 0; kk < 8; ++kk) {
+                    acc0 = mfma4(IL[cc * TP + 4 * kk + g], bv[kk], acc0);
+                    acc1 = mfma4(IL[(16 + cc) * TP + 4 * kk + g], bv[kk], acc1);
+                }
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = g + 4 * v, col = 16 * u + cc;
+                    out[(size_t)(j0 + row) * M + j0 + NP_NB + col] = acc0[v];
+                    out[(size_t)(j0 + 16 + row) * M + j0 + NP_NB + col] = acc1[v];
+                    UP[row * UPP + col] = acc0[v];
+                    UP[(16 + row) * UPP + col] = acc1[v];
+                }
+            }
+        }
+        if (__ballot(!okp) != 0ull && lane == 0) FL[0] = 1;
+        __syncthreads();
+        if (FL[0]) return false;
+        // ---- U: A22 -= L21 U12, two tiles per wave at a time (two MFMA chains)
+        const int nu = nt2 * nt2;
+        const double* cbase = src + (size_t)(j0 + NP_NB) * M + j0 + NP_NB;
+        double* obase = out + (size_t)(j0 + NP_NB) * M + j0 + NP_NB;
+        for (int q0 = w; q0 < nu; q0 += 2 * NW) {
+            const int q1 = min(q0 + NW, nu - 1);   // the second tile (the first again past the end, unused)
+            const int t0 = q0 / nt2, u0 = q0 - t0 * nt2, t1 = q1 / nt2, u1 = q1 - t1 * nt2;
+            v4d c0, c1;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                c0[v] = cbase[(size_t)(16 * t0 + g + 4 * v) * M + 16 * u0 + cc];
+                c1[v] = cbase[(size_t)(16 * t1 + g + 4 * v) * M + 16 * u1 + cc];
+            }
+#pragma unroll
+            for (int kk = 0; kk < 8; ++kk) {
+                const double b0 = UP[(4 * kk + g) * UPP + 16 * u0 + cc];
+                const double b1 = UP[(4 * kk + g) * UPP + 16 * u1 + cc];
+                c0 = mfma4(-LP[(16 * t0 + cc) * LPP + 4 * kk + g], b0, c0);
+                c1 = mfma4(-LP[(16 * t1 + cc) * LPP + 4 * kk + g], b1, c1);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) obase[(size_t)(16 * t0 + g + 4 * v) * M + 16 * u0 + cc] = c0[v];
+            if (q0 + NW < nu) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) obase[(size_t)(16 * t1 + g + 4 * v) * M + 16 * u1 + cc] = c1[v];
+            }
+        }
+        __syncthreads();
+    }
+    for (int q = tid; q < M; q += LW_NT) perm[q] = q;
+    return true;
+}
+
 __global__ __launch_bounds__(LW_NT) void k_getrf_pw(const KArgs ka) {
     constexpr int NB = LW_NB, P = LW_P;
     const Level& L = ka.L;
@@ -1049,6 +1329,10 @@ __global__ __launch_bounds__(LW_NT) void k_getrf_pw(const KArgs ka) {
     int* perm = L.perm + (size_t)i * M;
     extern __shared__ double sm_raw[];
     char* smc = (char*)sm_raw;
+    // the case without row interchanges first; the factorisation with
+    // interchanges below when a check of it fails
+    if ((M & (NP_NB - 1)) == 0 && getrf_nointerchange(a, out, perm, M, smc)) return;
+    __syncthreads();   // its LDS is reused
     constexpr LwLds lay = lw_lds_layout();
     double* NX = (double*)(smc + lay.nx);
     double* LB = (double*)(smc + lay.lb);
