@@ -1048,9 +1048,9 @@ __device__ __forceinline__ void lw_panel_steps(double (&v)[4][LW_NB], bool (&act
 // M x M block (M a multiple of 32, at most 256) is factored right-looking
 // in 32-column panels:
 //   D  one wave factors the 32 x 32 diagonal block A11 (one row per lane,
-//      the pivot row broadcast through LDS) and inverts L11 and U11
-//      (lanes 0-31 one column of inv(L11) each, lanes 32-63 one column of
-//      inv(U11), as forward substitutions);
+//      the pivot row broadcast through LDS) and inverts L11 and U11 (the
+//      four 16 x 16 diagonal blocks by forward substitution, a lane per
+//      column, the two off-diagonal blocks on MFMA);
 //   P  L21 = A21 inv(U11) and U12 = inv(L11) A12 on MFMA (all waves);
 //   U  A22 -= L21 U12 on MFMA, two 16 x 16 tiles per wave at a time.
 // Every pivot is checked to be finite and non-zero and every multiplier
@@ -1067,7 +1067,8 @@ struct NpLds {
 
 // t11: the factored diagonal block, f11 the same block flipped; il, iu:
 // inv(L11), inv(U11); ds: 32 ones, the reciprocals of the diagonal of U11
-// in reverse order, then in order (published during the factorisation); lp: L21 (rows below the block x 32);
+// in the order of its flipped 16 x 16 blocks, then the reciprocals of the
+// pivots published during the factorisation; lp: L21 (rows below the block x 32);
 // up: U12 (32 x columns right of the block); flag: failure of a check.
 __host__ __device__ constexpr NpLds np_lds_layout() {
     NpLds l{};
@@ -1102,24 +1103,35 @@ __device__ __forceinline__ bool np_diag(const double* __restrict__ src, double* 
     }
     bool ok = true;
     double* RP = DS + 64;   // reciprocal of each pivot, published with its row
+    // every lane's reciprocal of its own entry in the next pivot column, so
+    // that the pivot's lane has it ready when it publishes its row
+    auto recip = [](double x) {
+        double rc = __builtin_amdgcn_rcp(x);
+        rc = fma(rc, fma(-x, rc, 1.0), rc);
+        return fma(rc, fma(-x, rc, 1.0), rc);
+    };
+    double rcv = recip(v[0]);
 #pragma unroll
     for (int c = 0; c < 32; ++c) {
         // the lane index made opaque per step: the step's lane masks are
         // formed here, not all 64 of them up front (scalar register pressure)
         int ln = lane;
         __asm__ volatile("" : "+v"(ln));
-        // row c is final: its lane publishes it from c on, with 1 / pivot
+        // row c is final: its lane publishes it from c on, with 1 / pivot.
+        // The reads below need no wait for these writes: the LDS executes
+        // one wave's accesses in the order they were issued.
         if (ln == c) {
-            double rc = __builtin_amdgcn_rcp(v[c]);
-            rc = fma(rc, fma(-v[c], rc, 1.0), rc);
-            rc = fma(rc, fma(-v[c], rc, 1.0), rc);
-            RP[c] = rc;
+            RP[c] = rcv;
 #pragma unroll
             for (int q = 0; q < 32; ++q)
                 if (q >= c) T[c * TP + q] = v[q];
         }
-        wave_lds_sync();
-        const double pv = T[c * TP + c];
+        // the pivot row through one base register per step (immediate
+        // offsets below 256 doubles: pairs of reads share it)
+        int tb = c * TP;
+        __asm__ volatile("" : "+v"(tb));
+        const double* Tc = T + tb;
+        const double pv = Tc[c];
         const double rp = RP[c];
         ok = ok && pv != 0.0 && isfinite(pv);
         const bool act = ln < 32 && (ln & 31) > c;
@@ -1130,10 +1142,16 @@ __device__ __forceinline__ bool np_diag(const double* __restrict__ src, double* 
         // their v[c] is never read again
         const double le = act ? l : 0.0;
         v[c] = l;
+        if (c + 1 < 32) {
+            // the next pivot column first, and its reciprocal
+            v[c + 1] = fma(-le, Tc[c + 1], v[c + 1]);
+            rcv = recip(v[c + 1]);
+        }
 #pragma unroll
         for (int q = 0; q < 32; ++q)
-            if (q > c) v[q] = fma(-le, T[c * TP + q], v[q]);
+            if (q > c + 1) v[q] = fma(-le, Tc[q], v[q]);
     }
+    wave_lds_sync();
     // the factored rows: the multipliers left of the diagonal join the U
     // parts already in T; then the rows to out, and the block flipped,
     // F[a][b] = T[31-a][31-b], whose lower triangle is U11 reversed
@@ -1154,36 +1172,81 @@ __device__ __forceinline__ bool np_diag(const double* __restrict__ src, double* 
         }
     }
     wave_lds_sync();
+    // reciprocals of the diagonal of U11, in the order of the flipped blocks
     if (rowl) {
-        DS[32 + 31 - r] = 1.0 / T[r * TP + r];
         DS[r] = 1.0;
+        DS[r < 16 ? 32 + 15 - r : 48 + 31 - r] = 1.0 / T[r * TP + r];
     }
     wave_lds_sync();
-    // inverses by forward substitution with a lower triangle: lanes 0-31
-    // column j of inv(L11) (unit diagonal, the lower triangle of T); lanes
-    // 32-63 column 31-j of inv(U') for U' the lower triangle of F, whose
-    // inverse is inv(U11) reversed: inv(U11)[31-a][j] = inv(U')[a][31-j]
-    const bool up = !rowl;
-    const int jt = up ? 31 - r : r;
-    const double* Mh = up ? F : T;
-    const double* Dh = DS + (up ? 32 : 0);
-    double x[32];
-#pragma unroll
-    for (int a = 0; a < 32; ++a) {
-        // four partial sums: a short dependent chain per row (the unit
-        // column's index opaque per row: no 32 masks formed up front)
+    // The inverses in 16 x 16 blocks.  Lane group k = lane >> 4 inverts one
+    // diagonal block by forward substitution, lane j its column j: k = 0, 1
+    // the unit lower blocks L1 = L11[0:16, 0:16], L2 = L11[16:32, 16:32] (in
+    // T); k = 2, 3 the upper blocks U1 = U11[0:16, 0:16], U2 = U11[16:32,
+    // 16:32] through their flips U'[a][b] = U[15-a][15-b], lower triangles of
+    // F, with inv(U)[15-a][j] = inv(U')[a][15-j].
+    const int k4 = lane >> 4, j16 = lane & 15;
+    const bool uk = k4 >= 2;
+    const double* Mk = (k4 & 1) ? (uk ? F : T + 16 * TP + 16) : (uk ? F + 16 * TP + 16 : T);
+    const double* Dk = DS + 16 * k4;
+    const int jt = uk ? 15 - j16 : j16;
+    // right-looking: once x[b] is final, it is removed from every later
+    // row's sum (a dependent chain of one product per step; the loads of a
+    // column do not wait for x)
+    double x[16];
+    {
         int jo = jt;
         __asm__ volatile("" : "+v"(jo));
-        double s4[4] = {a == jo ? 1.0 : 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int b = 0; b < 32; ++b)
-            if (b < a) s4[b & 3] = fma(-Mh[a * TP + b], x[b], s4[b & 3]);
-        x[a] = ((s4[0] + s4[1]) + (s4[2] + s4[3])) * Dh[a];
+        for (int a = 0; a < 16; ++a) x[a] = a == jo ? 1.0 : 0.0;
     }
 #pragma unroll
-    for (int a = 0; a < 32; ++a) {
-        double* d = up ? IU + (31 - a) * TP + r : IL + a * TP + r;   // no branch: keeps x in registers
-        *d = x[a];
+    for (int b = 0; b < 16; ++b) {
+        x[b] *= Dk[b];
+#pragma unroll
+        for (int a = 0; a < 16; ++a)
+            if (a > b) x[a] = fma(-Mk[a * TP + b], x[b], x[a]);
+    }
+    {
+        const int ro = (k4 & 1) * 16;
+#pragma unroll
+        for (int a = 0; a < 16; ++a) {
+            double* d = uk ? IU + (ro + 15 - a) * TP + ro + j16 : IL + (ro + a) * TP + ro + j16;
+            *d = x[a];
+        }
+        // the zero blocks: inv(L11)[0:16, 16:32] (group 0), inv(U11)[16:32, 0:16] (group 3)
+        if (k4 == 0 || k4 == 3) {
+#pragma unroll
+            for (int a = 0; a < 16; ++a) {
+                double* z = k4 == 0 ? IL + a * TP + 16 + j16 : IU + (16 + a) * TP + j16;
+                *z = 0.0;
+            }
+        }
+    }
+    wave_lds_sync();
+    // the off-diagonal blocks on MFMA:
+    //   inv(L11)[16:32, 0:16] = -inv(L2) (L11[16:32, 0:16] inv(L1)),
+    //   inv(U11)[0:16, 16:32] = -inv(U1) (U11[0:16, 16:32] inv(U2));
+    // a product's output register v of lane group g holds row g + 4v, which
+    // is the right operand of slice v of the next product as it stands
+    {
+        const int g = lane >> 4, cc = lane & 15;
+        v4d y = {0.0, 0.0, 0.0, 0.0}, yu = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+            y = mfma4(T[(16 + cc) * TP + 4 * kk + g], IL[(4 * kk + g) * TP + cc], y);
+            yu = mfma4(T[cc * TP + 16 + 4 * kk + g], IU[(16 + 4 * kk + g) * TP + 16 + cc], yu);
+        }
+        v4d z = {0.0, 0.0, 0.0, 0.0}, zu = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+            z = mfma4(IL[(16 + cc) * TP + 16 + 4 * kk + g], y[kk], z);
+            zu = mfma4(IU[cc * TP + 4 * kk + g], yu[kk], zu);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            IL[(16 + g + 4 * v) * TP + cc] = -z[v];
+            IU[(g + 4 * v) * TP + 16 + cc] = -zu[v];
+        }
     }
     return ok;
 }
@@ -1315,7 +1378,7 @@ __device__ __forceinline__ bool getrf_nointerchange(const double* __restrict__ a
     return true;
 }
 
-__global__ __launch_bounds__(LW_NT) void k_getrf_pw(const KArgs ka) {
+__global__ __launch_bounds__(LW_NT) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_getrf_pw(const KArgs ka) {
     constexpr int NB = LW_NB, P = LW_P;
     const Level& L = ka.L;
     const int kch = ka.c0 + blockIdx.x, t = ka.step;
