@@ -1077,14 +1077,14 @@ __host__ __device__ constexpr NpLds np_lds_layout() {
     l.il = off; off += sizeof(double) * NP_NB * NP_TP;
     l.iu = off; off += sizeof(double) * NP_NB * NP_TP;
     l.ds = off; off += sizeof(double) * 3 * NP_NB;
+    l.f11 = off; off += sizeof(double) * NP_NB * NP_TP;
     l.lp = off; off += sizeof(double) * (256 - NP_NB) * NP_LPP;
-    l.f11 = l.lp;   // F is needed only before L21 is formed
     l.up = off; off += sizeof(double) * NP_NB * NP_UPP;
     l.flag = off; off += 16;
     l.total = off;
     return l;
 }
-static_assert(np_lds_layout().total <= lw_lds_layout().total, "no-interchange LU must fit the LU's LDS");
+static_assert(np_lds_layout().total <= 160 * 1024, "no-interchange LU must fit the LDS");
 
 // Phase D on one wave: factor A11 (rows j0.. of src, columns j0..) into T and
 // out, inverses into IL and IU.  Returns this lane's checks.
@@ -1251,6 +1251,36 @@ __device__ __forceinline__ bool np_diag(const double* __restrict__ src, double* 
     return ok;
 }
 
+// Two 16 x 16 tiles (t0, u0), (t1, u1) of the trailing matrix right of and
+// below the diagonal block at j0: A22 -= L21 U12 (L21, U12 in LDS), read from
+// src, written to out; the second tile is stored only if `second`.
+__device__ __forceinline__ void np_tiles(const double* __restrict__ src, double* __restrict__ out, int M, int j0,
+                                         int g, int cc, const double* LP, const double* UP, int t0, int u0, int t1,
+                                         int u1, bool second) {
+    constexpr int LPP = NP_LPP, UPP = NP_UPP;
+    const double* cbase = src + (size_t)(j0 + NP_NB) * M + j0 + NP_NB;
+    double* obase = out + (size_t)(j0 + NP_NB) * M + j0 + NP_NB;
+    v4d c0, c1;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        c0[v] = cbase[(size_t)(16 * t0 + g + 4 * v) * M + 16 * u0 + cc];
+        c1[v] = cbase[(size_t)(16 * t1 + g + 4 * v) * M + 16 * u1 + cc];
+    }
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) {
+        const double b0 = UP[(4 * kk + g) * UPP + 16 * u0 + cc];
+        const double b1 = UP[(4 * kk + g) * UPP + 16 * u1 + cc];
+        c0 = mfma4(-LP[(16 * t0 + cc) * LPP + 4 * kk + g], b0, c0);
+        c1 = mfma4(-LP[(16 * t1 + cc) * LPP + 4 * kk + g], b1, c1);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) obase[(size_t)(16 * t0 + g + 4 * v) * M + 16 * u0 + cc] = c0[v];
+    if (second) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) obase[(size_t)(16 * t1 + g + 4 * v) * M + 16 * u1 + cc] = c1[v];
+    }
+}
+
 // The no-interchange factorisation of one block; false (nothing but out
 // written) when a check fails.  Called by all threads of the LU workgroup.
 __device__ __forceinline__ bool getrf_nointerchange(const double* __restrict__ a, double* __restrict__ out, int* __restrict__ perm,
@@ -1277,102 +1307,101 @@ __device__ __forceinline__ bool getrf_nointerchange(const double* __restrict__ a
     constexpr int NW = LW_NT / 64;
     if (tid == 0) FL[0] = 0;
     __syncthreads();
-    for (int j0 = 0; j0 < M; j0 += NP_NB) {
+    // Iteration j0 = -32 factors only the first diagonal block; iteration
+    // j0 >= 0 forms L21, U12 of the block at j0, updates the next diagonal
+    // block, then factors it (wave 0) while the other waves update the rest
+    // of the trailing matrix.  One call site of np_diag (code size, registers).
+    for (int j0 = -NP_NB; j0 + NP_NB < M; j0 += NP_NB) {
+        const double* src = j0 <= 0 ? a : out;   // the trailing matrix: the working copy, then out
+        const int m2 = M - j0 - NP_NB;            // rows below = columns right of the block
         // per-lane offsets made opaque per panel, so that the products' lane
         // addresses are not hoisted out of the loop and kept live across the
         // diagonal block (register pressure)
         int lv = lane;
         __asm__ volatile("" : "+v"(lv));
         const int g = lv >> 4, cc = lv & 15;
-        const double* src = j0 == 0 ? a : out;   // the trailing matrix: the working copy, then out
-        const int m2 = M - j0 - NP_NB;            // rows below = columns right of the block
-        if (w == 0) {
-            const bool ok = np_diag(src, out, M, j0, T, F, IL, IU, DS, lane);
-            if (__ballot(!ok) != 0ull && lane == 0) FL[0] = 1;
-        }
-        __syncthreads();
-        if (FL[0]) return false;
-        if (m2 == 0) break;
         const int nt2 = m2 / 16;
-        // ---- P: L21 = A21 inv(U11) by 16-row blocks (tasks q < nt2) and
-        // U12 = inv(L11) A12 by 16-column blocks; a task reads all 32 columns
-        // (rows) of its block before it overwrites them (in place from the
-        // second panel on), so no two tasks share a block
-        bool okp = true;
-        for (int q = w; q < 2 * nt2; q += NW) {
-            v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
-            if (q < nt2) {
-                const double* arow = src + (size_t)(j0 + NP_NB + 16 * q + cc) * M + j0 + g;
-                double av[8];
+        if (j0 >= 0) {
+            // ---- P: L21 = A21 inv(U11) by 16-row blocks (tasks q < nt2) and
+            // U12 = inv(L11) A12 by 16-column blocks; a task reads all 32 columns
+            // (rows) of its block before it overwrites them (in place from the
+            // second panel on), so no two tasks share a block
+            bool okp = true;
+            for (int q = w; q < 2 * nt2; q += NW) {
+                v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+                if (q < nt2) {
+                    const double* arow = src + (size_t)(j0 + NP_NB + 16 * q + cc) * M + j0 + g;
+                    double av[8];
 #pragma unroll
-                for (int kk = 0; kk < 8; ++kk) av[kk] = arow[4 * kk];
+                    for (int kk = 0; kk < 8; ++kk) av[kk] = arow[4 * kk];
 #pragma unroll
-                for (int kk = 0; kk < 8; ++kk) {
-                    acc0 = mfma4(av[kk], IU[(4 * kk + g) * TP + cc], acc0);
-                    acc1 = mfma4(av[kk], IU[(4 * kk + g) * TP + 16 + cc], acc1);
-                }
+                    for (int kk = 0; kk < 8; ++kk) {
+                        acc0 = mfma4(av[kk], IU[(4 * kk + g) * TP + cc], acc0);
+                        acc1 = mfma4(av[kk], IU[(4 * kk + g) * TP + 16 + cc], acc1);
+                    }
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int row = 16 * q + g + 4 * v;
-                    okp = okp && fabs(acc0[v]) <= 1.0 && fabs(acc1[v]) <= 1.0;
-                    double* orow = out + (size_t)(j0 + NP_NB + row) * M + j0;
-                    orow[cc] = acc0[v];
-                    orow[16 + cc] = acc1[v];
-                    LP[row * LPP + cc] = acc0[v];
-                    LP[row * LPP + 16 + cc] = acc1[v];
-                }
-            } else {
-                const int u = q - nt2;
-                const double* bcol = src + (size_t)(j0 + g) * M + j0 + NP_NB + 16 * u + cc;
-                double bv[8];
+                    for (int v = 0; v < 4; ++v) {
+                        const int row = 16 * q + g + 4 * v;
+                        okp = okp && fabs(acc0[v]) <= 1.0 && fabs(acc1[v]) <= 1.0;
+                        double* orow = out + (size_t)(j0 + NP_NB + row) * M + j0;
+                        orow[cc] = acc0[v];
+                        orow[16 + cc] = acc1[v];
+                        LP[row * LPP + cc] = acc0[v];
+                        LP[row * LPP + 16 + cc] = acc1[v];
+                    }
+                } else {
+                    const int u = q - nt2;
+                    const double* bcol = src + (size_t)(j0 + g) * M + j0 + NP_NB + 16 * u + cc;
+                    double bv[8];
 #pragma unroll
-                for (int kk = 0; kk < 8; ++kk) bv[kk] = bcol[(size_t)4 * kk * M];
+                    for (int kk = 0; kk < 8; ++kk) bv[kk] = bcol[(size_t)4 * kk * M];
 #pragma unroll
-                for (int kk = 0; kk < 8; ++kk) {
-                    acc0 = mfma4(IL[cc * TP + 4 * kk + g], bv[kk], acc0);
-                    acc1 = mfma4(IL[(16 + cc) * TP + 4 * kk + g], bv[kk], acc1);
-                }
+                    for (int kk = 0; kk < 8; ++kk) {
+                        acc0 = mfma4(IL[cc * TP + 4 * kk + g], bv[kk], acc0);
+                        acc1 = mfma4(IL[(16 + cc) * TP + 4 * kk + g], bv[kk], acc1);
+                    }
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int row = g + 4 * v, col = 16 * u + cc;
-                    out[(size_t)(j0 + row) * M + j0 + NP_NB + col] = acc0[v];
-                    out[(size_t)(j0 + 16 + row) * M + j0 + NP_NB + col] = acc1[v];
-                    UP[row * UPP + col] = acc0[v];
-                    UP[(16 + row) * UPP + col] = acc1[v];
+                    for (int v = 0; v < 4; ++v) {
+                        const int row = g + 4 * v, col = 16 * u + cc;
+                        out[(size_t)(j0 + row) * M + j0 + NP_NB + col] = acc0[v];
+                        out[(size_t)(j0 + 16 + row) * M + j0 + NP_NB + col] = acc1[v];
+                        UP[row * UPP + col] = acc0[v];
+                        UP[(16 + row) * UPP + col] = acc1[v];
+                    }
                 }
             }
+            if (__ballot(!okp) != 0ull && lane == 0) FL[0] = 1;
+            __syncthreads();
+            if (FL[0]) return false;
         }
-        if (__ballot(!okp) != 0ull && lane == 0) FL[0] = 1;
+        // ---- U: A22 -= L21 U12.  The next diagonal block's four tiles
+        // first (waves 0-1); then wave 0 factors that block while waves 1-7
+        // update the other tiles, two at a time (two MFMA chains).
+        if (j0 >= 0) {
+            // the 2 x 2 tiles of the next diagonal block
+            if (w < 2) np_tiles(src, out, M, j0, g, cc, LP, UP, w, 0, w, 1, true);
+            __syncthreads();
+        }
+        if (w == 0) {
+            const bool ok = np_diag(j0 < 0 ? a : out, out, M, j0 + NP_NB, T, F, IL, IU, DS, lane);
+            if (__ballot(!ok) != 0ull && lane == 0) FL[0] = 1;
+        } else if (j0 >= 0) {
+            // the other tiles: rows 0-1 right of the block, then rows 2..
+            const int w1 = nt2 - 2, nr = nt2 * nt2 - 4;
+            auto tile_of = [&](int k, int& t, int& u) {
+                if (k < 2 * w1) { t = k / w1; u = 2 + k - t * w1; }
+                else { const int k2 = k - 2 * w1; t = 2 + k2 / nt2; u = k2 - (t - 2) * nt2; }
+            };
+            for (int k0 = w - 1; k0 < nr; k0 += 2 * (NW - 1)) {
+                const int k1 = min(k0 + NW - 1, nr - 1);   // the second tile (the first again past the end, unused)
+                int t0, u0, t1, u1;
+                tile_of(k0, t0, u0);
+                tile_of(k1, t1, u1);
+                np_tiles(src, out, M, j0, g, cc, LP, UP, t0, u0, t1, u1, k0 + NW - 1 < nr);
+            }
+        }
         __syncthreads();
         if (FL[0]) return false;
-        // ---- U: A22 -= L21 U12, two tiles per wave at a time (two MFMA chains)
-        const int nu = nt2 * nt2;
-        const double* cbase = src + (size_t)(j0 + NP_NB) * M + j0 + NP_NB;
-        double* obase = out + (size_t)(j0 + NP_NB) * M + j0 + NP_NB;
-        for (int q0 = w; q0 < nu; q0 += 2 * NW) {
-            const int q1 = min(q0 + NW, nu - 1);   // the second tile (the first again past the end, unused)
-            const int t0 = q0 / nt2, u0 = q0 - t0 * nt2, t1 = q1 / nt2, u1 = q1 - t1 * nt2;
-            v4d c0, c1;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                c0[v] = cbase[(size_t)(16 * t0 + g + 4 * v) * M + 16 * u0 + cc];
-                c1[v] = cbase[(size_t)(16 * t1 + g + 4 * v) * M + 16 * u1 + cc];
-            }
-#pragma unroll
-            for (int kk = 0; kk < 8; ++kk) {
-                const double b0 = UP[(4 * kk + g) * UPP + 16 * u0 + cc];
-                const double b1 = UP[(4 * kk + g) * UPP + 16 * u1 + cc];
-                c0 = mfma4(-LP[(16 * t0 + cc) * LPP + 4 * kk + g], b0, c0);
-                c1 = mfma4(-LP[(16 * t1 + cc) * LPP + 4 * kk + g], b1, c1);
-            }
-#pragma unroll
-            for (int v = 0; v < 4; ++v) obase[(size_t)(16 * t0 + g + 4 * v) * M + 16 * u0 + cc] = c0[v];
-            if (q0 + NW < nu) {
-#pragma unroll
-                for (int v = 0; v < 4; ++v) obase[(size_t)(16 * t1 + g + 4 * v) * M + 16 * u1 + cc] = c1[v];
-            }
-        }
-        __syncthreads();
     }
     for (int q = tid; q < M; q += LW_NT) perm[q] = q;
     return true;
@@ -2808,7 +2837,7 @@ hipError_t launch_recover(const KArgs& ka, hipStream_t s) {
 static bool getrf_small(int M) { return M <= 256; }
 
 size_t getrf_lds_bytes(int M) {
-    return getrf_small(M) ? lw_lds_layout().total : lu_lds_layout(M, 512, 16).total;
+    return getrf_small(M) ? std::max(lw_lds_layout().total, np_lds_layout().total) : lu_lds_layout(M, 512, 16).total;
 }
 
 hipError_t launch_getrf(const KArgs& ka, hipStream_t s) {
