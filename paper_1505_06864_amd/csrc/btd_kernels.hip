@@ -1048,7 +1048,7 @@ __device__ __forceinline__ void lw_panel_steps(double (&v)[4][LW_NB], bool (&act
 // M x M block (M a multiple of 32, at most 256) is factored right-looking
 // in 32-column panels:
 //   D  one wave factors the 32 x 32 diagonal block A11 (one row per lane,
-//      the pivot row broadcast through LDS) and inverts L11 and U11 (the
+//      the pivot row read from its lane) and inverts L11 and U11 (the
 //      four 16 x 16 diagonal blocks by forward substitution, a lane per
 //      column, the two off-diagonal blocks on MFMA);
 //   P  L21 = A21 inv(U11) and U12 = inv(L11) A12 on MFMA (all waves);
@@ -1066,9 +1066,8 @@ struct NpLds {
 };
 
 // t11: the factored diagonal block, f11 the same block flipped; il, iu:
-// inv(L11), inv(U11); ds: 32 ones, the reciprocals of the diagonal of U11
-// in the order of its flipped 16 x 16 blocks, then the reciprocals of the
-// pivots published during the factorisation; lp: L21 (rows below the block x 32);
+// inv(L11), inv(U11); ds: 32 ones, then the reciprocals of the diagonal of
+// U11 in the order of its flipped 16 x 16 blocks; lp: L21 (rows below the block x 32);
 // up: U12 (32 x columns right of the block); flag: failure of a check.
 __host__ __device__ constexpr NpLds np_lds_layout() {
     NpLds l{};
@@ -1076,7 +1075,7 @@ __host__ __device__ constexpr NpLds np_lds_layout() {
     l.t11 = off; off += sizeof(double) * NP_NB * NP_TP;
     l.il = off; off += sizeof(double) * NP_NB * NP_TP;
     l.iu = off; off += sizeof(double) * NP_NB * NP_TP;
-    l.ds = off; off += sizeof(double) * 3 * NP_NB;
+    l.ds = off; off += sizeof(double) * 2 * NP_NB;
     l.f11 = off; off += sizeof(double) * NP_NB * NP_TP;
     l.lp = off; off += sizeof(double) * (256 - NP_NB) * NP_LPP;
     l.up = off; off += sizeof(double) * NP_NB * NP_UPP;
@@ -1102,9 +1101,8 @@ __device__ __forceinline__ bool np_diag(const double* __restrict__ src, double* 
         v[c + 1] = x.y;
     }
     bool ok = true;
-    double* RP = DS + 64;   // reciprocal of each pivot, published with its row
-    // every lane's reciprocal of its own entry in the next pivot column, so
-    // that the pivot's lane has it ready when it publishes its row
+    // every lane's reciprocal of its own entry in the next pivot column; the
+    // pivot's lane holds the one needed
     auto recip = [](double x) {
         double rc = __builtin_amdgcn_rcp(x);
         rc = fma(rc, fma(-x, rc, 1.0), rc);
@@ -1117,58 +1115,39 @@ __device__ __forceinline__ bool np_diag(const double* __restrict__ src, double* 
         // formed here, not all 64 of them up front (scalar register pressure)
         int ln = lane;
         __asm__ volatile("" : "+v"(ln));
-        // row c is final: its lane publishes it from c on, with 1 / pivot.
-        // The reads below need no wait for these writes: the LDS executes
-        // one wave's accesses in the order they were issued.
-        if (ln == c) {
-            RP[c] = rcv;
-#pragma unroll
-            for (int q = 0; q < 32; ++q)
-                if (q >= c) T[c * TP + q] = v[q];
-        }
-        // the pivot row through one base register per step (immediate
-        // offsets below 256 doubles: pairs of reads share it)
-        int tb = c * TP;
-        __asm__ volatile("" : "+v"(tb));
-        const double* Tc = T + tb;
-        const double pv = Tc[c];
-        const double rp = RP[c];
+        // the pivot row and its reciprocal read straight from lane c (no
+        // LDS round trip on the chain of column steps)
+        const double pv = readlane_d(v[c], c);
+        const double rp = readlane_d(rcv, c);
         ok = ok && pv != 0.0 && isfinite(pv);
         const bool act = ln < 32 && (ln & 31) > c;
         const double l = v[c] * rp;
         ok = ok && (!act || fabs(l) <= 1.0);
-        // no branch: the rows above get a zero multiple (a non-finite pivot
-        // row fails the checks later on) and keep their U part in T, so
-        // their v[c] is never read again
+        // rows above get a zero multiple (a non-finite pivot row fails the
+        // checks later on) and keep their values
         const double le = act ? l : 0.0;
-        v[c] = l;
+        v[c] = act ? l : v[c];
         if (c + 1 < 32) {
             // the next pivot column first, and its reciprocal
-            v[c + 1] = fma(-le, Tc[c + 1], v[c + 1]);
+            v[c + 1] = fma(-le, readlane_d(v[c + 1], c), v[c + 1]);
             rcv = recip(v[c + 1]);
         }
 #pragma unroll
         for (int q = 0; q < 32; ++q)
-            if (q > c + 1) v[q] = fma(-le, Tc[q], v[q]);
+            if (q > c + 1) v[q] = fma(-le, readlane_d(v[q], c), v[q]);
     }
-    wave_lds_sync();
-    // the factored rows: the multipliers left of the diagonal join the U
-    // parts already in T; then the rows to out, and the block flipped,
-    // F[a][b] = T[31-a][31-b], whose lower triangle is U11 reversed
-    if (rowl) {
-#pragma unroll
-        for (int q = 0; q < 32; ++q)
-            if (q < r) T[r * TP + q] = v[q];
-    }
-    wave_lds_sync();
+    // the factored rows (multipliers left of the diagonal, U from it) to
+    // T and out, and the block flipped, F[a][b] = T[31-a][31-b], whose lower
+    // triangle is U11 reversed
     if (rowl) {
         double* orow = out + (size_t)(j0 + r) * M + j0;
 #pragma unroll
         for (int q = 0; q < 32; q += 2) {
-            const double t0 = T[r * TP + q], t1 = T[r * TP + q + 1];
-            *(double2*)(orow + q) = make_double2(t0, t1);
-            F[(31 - r) * TP + 31 - q] = t0;
-            F[(31 - r) * TP + 30 - q] = t1;
+            T[r * TP + q] = v[q];
+            T[r * TP + q + 1] = v[q + 1];
+            *(double2*)(orow + q) = make_double2(v[q], v[q + 1]);
+            F[(31 - r) * TP + 31 - q] = v[q];
+            F[(31 - r) * TP + 30 - q] = v[q + 1];
         }
     }
     wave_lds_sync();
