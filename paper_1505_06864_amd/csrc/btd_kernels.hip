@@ -2100,7 +2100,11 @@ __device__ __forceinline__ double4 tseq_load(int e, const double* __restrict__ l
                                              int M, int nblk, int tid, int& valid) {
     const int kind = tseq_kind<NBLK>(e), b = tseq_b<NBLK>(e), bp = tseq_bp<NBLK>(e);
     constexpr int PR = DB / PC;   // pieces per block row
-    const int r = tid / PR, c4 = (tid % PR) * PC;
+    // the thread index made opaque here: each element's address is formed
+    // where it is loaded instead of all of them up front (registers)
+    int to = tid;
+    __asm__ volatile("" : "+v"(to));
+    const int r = to / PR, c4 = (to % PR) * PC;
     double q[4] = {0.0, 0.0, 0.0, 0.0};
     valid = 0;
     if (kind == 0 || kind == 2) {
@@ -2211,6 +2215,37 @@ __device__ __forceinline__ void tseq_run(typename Acc4<CT>::type (&x)[NBLK][2][N
     }
 }
 
+// The same two elements per barrier (the number of elements is even):
+// elements E, E+1 were staged before the barrier that ends the previous
+// pair; stage E+2, E+3 (loaded two pairs ago), start loading E+6, E+7,
+// apply E and E+1, barrier.  q0..q3 hold the pieces of E+2 .. E+5 on entry.
+// The four ring slots of E .. E+3 are distinct.
+template <int NBLK, int NT16, int PC, int E, class CT = double>
+__device__ __forceinline__ void tseq_run2(typename Acc4<CT>::type (&x)[NBLK][2][NT16], CT* ring,
+                                          const double* __restrict__ lu, const double* __restrict__ di, int M,
+                                          int nblk, int tid, int lane, double4& q0, int n0, double4& q1, int n1,
+                                          double4& q2, int n2, double4& q3, int n3) {
+    constexpr int NS = trsm_nseq<NBLK>();
+    static_assert(NS % 2 == 0, "pairs of sequence elements");
+    if constexpr (E < NS) {
+        if constexpr (E + 2 < NS) {
+            tseq_stage<NBLK, PC, CT>(E + 2, ring + ((E + 2) % TS_RING) * TS_BLOCK, tid, q0, n0);
+            tseq_stage<NBLK, PC, CT>(E + 3, ring + ((E + 3) % TS_RING) * TS_BLOCK, tid, q1, n1);
+        }
+        double4 q4 = {0.0, 0.0, 0.0, 0.0}, q5 = {0.0, 0.0, 0.0, 0.0};
+        int n4 = 0, n5 = 0;
+        if constexpr (E + 6 < NS) {
+            q4 = tseq_load<NBLK, PC>(E + 6, lu, di, M, nblk, tid, n4);
+            q5 = tseq_load<NBLK, PC>(E + 7, lu, di, M, nblk, tid, n5);
+        }
+        tseq_apply<NBLK, NT16, E, CT>(x, ring + (E % TS_RING) * TS_BLOCK, lane);
+        __builtin_amdgcn_sched_barrier(0);   // one element's operands at a time (registers)
+        tseq_apply<NBLK, NT16, E + 1, CT>(x, ring + ((E + 1) % TS_RING) * TS_BLOCK, lane);
+        __syncthreads();
+        tseq_run2<NBLK, NT16, PC, E + 2, CT>(x, ring, lu, di, M, nblk, tid, lane, q2, n2, q3, n3, q4, n4, q5, n5);
+    }
+}
+
 // RHS: the right-hand-side sweep's X_i (R columns, in place) instead of
 // W_i = [C_i | -B_i Y_{i-1}].  CT: product type (float: FP32 MFMA with FP32
 // accumulation on the FP64 factors and right-hand side, for the
@@ -2243,10 +2278,13 @@ __global__ __launch_bounds__(64 * WPB) void k_getrs_s(const KArgs ka, int nslab,
     const int ld = RHS ? ka.R : 2 * M;
     // first blocks of the sequence in flight before the right-hand side is read
     constexpr int PC = 1024 / (64 * WPB);   // doubles of a staged block per thread
-    int m0, m1, m2;
+    int m0, m1, m2, m3, m4, m5;
     double4 p0 = tseq_load<NBLK, PC>(0, lu, di, M, nblk, tid, m0);
     double4 p1 = tseq_load<NBLK, PC>(1, lu, di, M, nblk, tid, m1);
     double4 p2 = tseq_load<NBLK, PC>(2, lu, di, M, nblk, tid, m2);
+    double4 p3 = tseq_load<NBLK, PC>(3, lu, di, M, nblk, tid, m3);
+    double4 p4 = tseq_load<NBLK, PC>(4, lu, di, M, nblk, tid, m4);
+    double4 p5 = tseq_load<NBLK, PC>(5, lu, di, M, nblk, tid, m5);
     // the right-hand side from the pivot rows (perm holds valid rows), every
     // load unconditional from a clamped row and column; zeros outside after
     // all loads are out.  The E half of W_i starts as C_i and is read from C
@@ -2288,8 +2326,9 @@ __global__ __launch_bounds__(64 * WPB) void k_getrs_s(const KArgs ka, int nslab,
                 }
             }
     tseq_stage<NBLK, PC, CT>(0, ring, tid, p0, m0);
+    tseq_stage<NBLK, PC, CT>(1, ring + TS_BLOCK, tid, p1, m1);
     __syncthreads();
-    tseq_run<NBLK, NT16, PC, 0, CT>(x, ring, lu, di, M, nblk, tid, lane, p1, m1, p2, m2);
+    tseq_run2<NBLK, NT16, PC, 0, CT>(x, ring, lu, di, M, nblk, tid, lane, p2, m2, p3, m3, p4, m4, p5, m5);
 #pragma unroll
     for (int b = 0; b < NBLK; ++b)
 #pragma unroll
