@@ -416,12 +416,13 @@ def bench_uneven(torch, args):
         del Fs
         groups.append((g, F))
     torch.cuda.synchronize()
-    tuner = batch.Tuner()
+    tuner = batch.Tuner(fused=args.schedule == "fused")
     chosen = [tuner.choose(g, F, args.prec) for g, F in groups]
     fmax = max(btd.workspace_bytes(g.N, g.M, P, d, g.R, None, c)[0] for (g, _), (P, d, c) in zip(groups, chosen))
     smax = max(btd.workspace_bytes(g.N, g.M, P, d, g.R, None, c)[1] for (g, _), (P, d, c) in zip(groups, chosen))
     shared = (torch.empty(fmax + 256, dtype=torch.uint8, device=dev), torch.empty(smax + 256, dtype=torch.uint8, device=dev))
-    runs = [batch.GroupRun(g, P, d, c, args.prec, shared=shared) for (g, _), (P, d, c) in zip(groups, chosen)]
+    runs = [batch.GroupRun(g, P, d, c, args.prec, shared=shared, fused=args.schedule == "fused")
+            for (g, _), (P, d, c) in zip(groups, chosen)]
 
     def step():
         for run, (g, F) in zip(runs, groups):
@@ -457,7 +458,8 @@ def bench_uneven(torch, args):
            "config": {"workload": f"uneven: {args.systems} systems, N ~ U{{32..1024}}, M in {{32,64,128,192}}, "
                                   f"R in {{1,8,32}}, diag_dominant_2.0 blocks drawn on the device, "
                                   + ("FP64" if args.prec == "f64" else "FP32 factor products + FP64 refinement"),
-                      "systems": args.systems, "rows": int(sum(g.N for g, _ in groups))},
+                      "systems": args.systems, "rows": int(sum(g.N for g, _ in groups)),
+                      "schedule": "fused" if runs[0].fused else "separate"},
            "tflops": fl / (ms * 1e-3) / 1e12, "frac_fp64_peak": fl / (ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
            "groups": [{"M": g.M, "systems": len(g.rows), "rows": g.N, "R": g.R, "P": P, "depth": d,
                        "coupling_rows": c} for (g, _), (P, d, c) in zip(groups, chosen)],

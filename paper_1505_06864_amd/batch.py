@@ -92,9 +92,11 @@ class Tuner:
     (the paper's optimum for one processor per subsystem), and 8, 16 and 32
     rows (on the GPU every subsystem of a step runs in the same launch, so
     shorter subsystems mean fewer sequential steps); each with one-row
-    coupling subsystems (depth 10) and with Eq. SuppMatrM's split (depth 2)."""
+    coupling subsystems (depth 10) and with Eq. SuppMatrM's split (depth 2).
+    fused: candidates timed as one btd_factor_solve call (prec f64)."""
 
-    def __init__(self):
+    def __init__(self, fused=False):
+        self.fused = fused
         self.cache = {}
         self.log = []
 
@@ -121,7 +123,7 @@ class Tuner:
         best = None
         for rows, depth, crow in self.candidates(g):
             P = self.parts(g, rows)
-            run = GroupRun(g, P, depth, crow, prec)
+            run = GroupRun(g, P, depth, crow, prec, fused=self.fused)
             run.step(F)            # warm (also builds the workspaces)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -143,12 +145,14 @@ class GroupRun:
     """Factor + solve of one stacked group through the C ABI with workspaces
     allocated once (graph-capturable for prec f64)."""
 
-    def __init__(self, g, P, depth, coupling_rows, prec="f64", stream=None, shared=None):
+    def __init__(self, g, P, depth, coupling_rows, prec="f64", stream=None, shared=None, fused=False):
         """shared: optional (factor buffer, solve buffer) uint8 tensors at least
         as large as this plan needs, reused by groups run one after another on
-        one stream."""
+        one stream.  fused (prec f64): factor and solve in one
+        btd_factor_solve call."""
         torch = _torch()
         self.g, self.prec = g, prec
+        self.fused = fused and prec == "f64"
         self.P, self.depth, self.coupling_rows = P, depth, coupling_rows
         self.L = btd.lib()
         self.desc, self._keep = btd.make_desc(g.N, g.M, P, depth, g.R, None, coupling_rows, prec)
@@ -177,6 +181,14 @@ class GroupRun:
         blocks on the residual norms)."""
         g, L = self.g, self.L
         h = ctypes.c_void_p()
+        if self.fused:
+            rc = L.btd_factor_solve(ctypes.byref(self.desc), g.A.data_ptr(), g.B.data_ptr(), g.C.data_ptr(),
+                                    self.fptr, self.fb, g.R, F.data_ptr(), self.X.data_ptr(), self.sptr, self.sb,
+                                    self.sh, ctypes.byref(h))
+            if rc:
+                raise btd.BtdError(rc, "btd_factor_solve")
+            self.plans.append(h)
+            return self.X
         rc = L.btd_factor(ctypes.byref(self.desc), g.A.data_ptr(), g.B.data_ptr(), g.C.data_ptr(), self.fptr,
                           self.fb, self.sh, ctypes.byref(h))
         if rc:

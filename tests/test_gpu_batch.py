@@ -26,18 +26,18 @@ def make_groups(torch, count=36, seed=5):
     return specs, systems, groups
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32_refine"])
-def test_batched_systems_match_oracle(prec):
+@pytest.mark.parametrize("prec,fused", [("f64", False), ("f64", True), ("f32_refine", False)])
+def test_batched_systems_match_oracle(prec, fused):
     torch = require_gpu()
     specs, systems, groups = make_groups(torch)
-    tuner = batch.Tuner()
+    tuner = batch.Tuner(fused=fused)
     for g, F in groups:
         P, depth, crow = tuner.choose(g, F, prec)
         print(f"group M={g.M} systems={len(g.rows)} rows={g.N} R={g.R} -> P={P} depth={depth} "
               f"coupling_rows={crow}", flush=True)
         assert 1 <= P <= (g.N + 1) // 2
         assert tuner.choose(g, F, prec) == (P, depth, crow)       # cached
-        run = batch.GroupRun(g, P, depth, crow, prec)
+        run = batch.GroupRun(g, P, depth, crow, prec, fused=fused)
         X = run.step(F)
         assert run.info() == (0, -1, -1)
         for s, x in zip(g.systems, g.split(X)):
@@ -50,7 +50,8 @@ def test_batched_systems_match_oracle(prec):
         run.release()
 
 
-def test_batched_graph_replay_matches_eager():
+@pytest.mark.parametrize("fused", [False, True])
+def test_batched_graph_replay_matches_eager(fused):
     torch = require_gpu()
     specs, systems, groups = make_groups(torch, count=20, seed=6)
     fmax = smax = 0
@@ -61,7 +62,7 @@ def test_batched_graph_replay_matches_eager():
         fmax, smax = max(fmax, f), max(smax, s)
     shared = (torch.empty(fmax + 256, dtype=torch.uint8, device="cuda"),
               torch.empty(smax + 256, dtype=torch.uint8, device="cuda"))
-    runs = [batch.GroupRun(g, P, d, c, "f64", shared=shared) for (g, _), (P, d, c) in zip(groups, params)]
+    runs = [batch.GroupRun(g, P, d, c, "f64", shared=shared, fused=fused) for (g, _), (P, d, c) in zip(groups, params)]
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
     for run in runs:
