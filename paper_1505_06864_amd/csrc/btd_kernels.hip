@@ -2567,75 +2567,108 @@ __global__ void k_write_ints(int* dst, int count, IntChunk vals) {
     if (t < count) dst[t] = vals.v[t];
 }
 
-// ------------------------------------------------------------------ recovery, few right-hand sides
+// ------------------------------------------------------------------ recovery and coupling right-hand side, one column
 //
-// X_i -= Z_L[i] h^{k-1} + Z_R[i] h^k (Eq. endSolution) for R <= RC and M a
-// multiple of 128: one workgroup per block row; each wave takes whole rows
-// of Z_i = [Z_L | Z_R] with its lanes covering the row in 32-byte pieces,
-// the matching pieces of [h^{k-1}; h^k] held in registers, four rows in
-// flight and a DPP sum per row (an HBM stream of 16 M^2 bytes per block row
-// for 4 M^2 R FLOPs).  Separator rows take their value from the coupling
-// solution.
-template <int RC>
+// Both are out = base - [M1 | M2] [v1; v2] over 16 rows per workgroup, with
+// M1, M2 two M x M blocks and v1, v2 two vectors of M entries (R = 1):
+//   recovery (Eq. endSolution), block row i of chunk k:
+//     X_i -= Z_L[i] h^{k-1} + Z_R[i] h^k   (in place; separator rows X_q = h)
+//   coupling right-hand side (Eq. e2311), separator q between chunks:
+//     Fc_j = F_q - B_q X_{q-1} - C_q X_{q+1}
+// M a multiple of 128 and the rows of M1, M2 32-byte aligned: each wave
+// takes four whole rows, its lanes covering the 2M columns of [M1 | M2] in
+// 32-byte pieces (column kk < M from M1, else column kk - M of M2), the
+// matching pieces of [v1; v2] in registers, all four rows' loads in flight
+// and a DPP sum per row (an HBM stream of 16 M^2 bytes per item for 4 M^2
+// FLOPs).  A block row is split over M / 16 workgroups so that a coupling
+// level with few block rows is not one workgroup's stream.
+constexpr int RV_ROWS = 16;                        // rows per workgroup
+constexpr int RV_MAXP = 2 * BTD_MAX_M / 256;       // 256-column pieces of a 2M row
+
+struct Gemv2 {
+    const double* M1;   // row r at M1 + r * ld1
+    const double* M2;
+    int ld1, ld2;
+    const double* v1;   // nullptr: that half is zero
+    const double* v2;
+    const double* base; // entry r at base[r]
+    double* out;        // entry r at out[r] (may alias base)
+};
+
+__device__ __forceinline__ void gemv2_rows(const Gemv2& g, int M, int r0, int lane) {
+    const int np = 2 * M / 256;
+    double hv[RV_MAXP][4];
+#pragma unroll
+    for (int q = 0; q < RV_MAXP; ++q)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int kk = q * 256 + 4 * lane + e;
+            const bool isl = kk < M;
+            const double* v = isl ? g.v1 : g.v2;
+            hv[q][e] = (q < np && v != nullptr) ? v[isl ? kk : kk - M] : 0.0;
+        }
+    double s[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        s[u] = 0.0;
+        const int r = r0 + u;
+#pragma unroll
+        for (int q = 0; q < RV_MAXP; ++q)
+            if (q < np) {
+                const int kk = q * 256 + 4 * lane;   // a piece lies in one of the halves (M % 4 == 0)
+                const double* src = kk < M ? g.M1 + (size_t)r * g.ld1 + kk : g.M2 + (size_t)r * g.ld2 + (kk - M);
+                const double4 zz = *(const double4*)src;
+                s[u] = fma(zz.x, hv[q][0], s[u]);
+                s[u] = fma(zz.y, hv[q][1], s[u]);
+                s[u] = fma(zz.z, hv[q][2], s[u]);
+                s[u] = fma(zz.w, hv[q][3], s[u]);
+            }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const double tot = wave_sum(s[u]);
+        if (lane == 0) g.out[r0 + u] = g.base[r0 + u] - tot;
+    }
+}
+
+// Recovery: blockIdx.x block row i, blockIdx.y its 16-row slice.
 __global__ __launch_bounds__(256) void k_recover_v(const KArgs ka) {
     const Level& L = ka.L;
-    const int i = blockIdx.x, M = L.M, R = ka.R, P = L.P;
-    const size_t MR = (size_t)M * R, MM = (size_t)M * M;
+    const int i = blockIdx.x, M = L.M, P = L.P;
+    const int row0 = blockIdx.y * RV_ROWS;
+    const size_t MM = (size_t)M * M;
     int lo = 0, hi = P;   // chunk k with sep[k] <= i < sep[k+1]  (sep[0] = -1, sep[P] = N)
     while (hi - lo > 1) { const int mid = (lo + hi) >> 1; if (L.sep[mid] <= i) lo = mid; else hi = mid; }
     const int k = lo;
-    double* Xi = ka.X + i * MR;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    if (L.sep[k] == i) {   // separator row: X_q = h^k
-        for (int e = threadIdx.x; e < (int)MR; e += 256) Xi[e] = ka.Fc[(size_t)(k - 1) * MR + e];
+    double* Xi = ka.X + (size_t)i * M;
+    if (L.sep[k] == i) {   // separator row: X_q = h^k (this workgroup's rows)
+        for (int e = row0 + threadIdx.x; e < min(row0 + RV_ROWS, M); e += 256) Xi[e] = ka.Fc[(size_t)(k - 1) * M + e];
         return;
     }
-    const bool left = k > 0, right = k < P - 1;
-    // lane l covers columns 4l..4l+3 of every 256-column piece of the 2M columns
-    constexpr int MAXP = 2 * BTD_MAX_M / 256;
-    const int np = 2 * M / 256;
-    double hv[MAXP][4][RC];
-#pragma unroll
-    for (int q = 0; q < MAXP; ++q)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int kk = q * 256 + 4 * lane + e;   // 0..2M-1: h^{k-1} rows then h^k rows
-            const bool isl = kk < M;
-            const bool ok = q < np && (isl ? left : right);
-            const double* hsrc = ka.Fc + (size_t)(isl ? k - 1 : k) * MR + (size_t)(isl ? kk : kk - M) * R;
-#pragma unroll
-            for (int c = 0; c < RC; ++c) hv[q][e][c] = (ok && c < R) ? hsrc[c] : 0.0;
-        }
     const double* Zi = L.Z + i * MM * 2;
-    for (int r0 = w * 4; r0 < M; r0 += 16) {
-        double s[4][RC];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-#pragma unroll
-            for (int c = 0; c < RC; ++c) s[u][c] = 0.0;
-            const double* z = Zi + (size_t)(r0 + u) * 2 * M + 4 * lane;
-#pragma unroll
-            for (int q = 0; q < MAXP; ++q)
-                if (q < np) {
-                    const double4 zz = *(const double4*)(z + q * 256);
-#pragma unroll
-                    for (int c = 0; c < RC; ++c) {
-                        s[u][c] = fma(zz.x, hv[q][0][c], s[u][c]);
-                        s[u][c] = fma(zz.y, hv[q][1][c], s[u][c]);
-                        s[u][c] = fma(zz.z, hv[q][2][c], s[u][c]);
-                        s[u][c] = fma(zz.w, hv[q][3][c], s[u][c]);
-                    }
-                }
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-            for (int c = 0; c < RC; ++c)
-                if (c < R) {
-                    const double tot = wave_sum(s[u][c]);
-                    if (lane == 0) Xi[(size_t)(r0 + u) * R + c] -= tot;
-                }
-    }
+    Gemv2 g;
+    g.M1 = Zi; g.ld1 = 2 * M;
+    g.M2 = Zi + M; g.ld2 = 2 * M;
+    g.v1 = k > 0 ? ka.Fc + (size_t)(k - 1) * M : nullptr;
+    g.v2 = k < P - 1 ? ka.Fc + (size_t)k * M : nullptr;
+    g.base = Xi; g.out = Xi;
+    gemv2_rows(g, M, row0 + (threadIdx.x >> 6) * 4, threadIdx.x & 63);
+}
+
+// Coupling right-hand side: blockIdx.x separator j (row q = sep[j+1]),
+// blockIdx.y its 16-row slice.
+__global__ __launch_bounds__(256) void k_couple_rhs_v(const KArgs ka) {
+    const Level& L = ka.L;
+    const int jj = blockIdx.x, M = L.M, q = L.sep[jj + 1];
+    const size_t MM = (size_t)M * M;
+    Gemv2 g;
+    g.M1 = L.B + q * MM; g.ld1 = M;
+    g.M2 = L.C + q * MM; g.ld2 = M;
+    g.v1 = ka.X + (size_t)(q - 1) * M;
+    g.v2 = ka.X + (size_t)(q + 1) * M;
+    g.base = ka.F + (size_t)q * M;
+    g.out = ka.Fc + (size_t)jj * M;
+    gemv2_rows(g, M, blockIdx.y * RV_ROWS + (threadIdx.x >> 6) * 4, threadIdx.x & 63);
 }
 
 // ------------------------------------------------------------------ residual
@@ -2840,10 +2873,20 @@ hipError_t launch_bwd_gemm(const KArgs& ka, hipStream_t s) {
                    : launch_gemm<GM_BWD, 2>(ka, ka.nc, ka.L.M, ka.L.M, s);
 }
 hipError_t launch_couple(const KArgs& ka, hipStream_t s) { return launch_gemm<GM_COUPLE, 3>(ka, ka.L.P - 1, ka.L.M, ka.L.M, s); }
-hipError_t launch_couple_rhs(const KArgs& ka, hipStream_t s) { return launch_gemm<GM_COUPLE_RHS, 1>(ka, ka.L.P - 1, ka.L.M, ka.R, s); }
+// The one-column forms need M a multiple of 128 and 32-byte aligned rows.
+static bool gemv2_ok(int M, int R, const void* a, const void* b) {
+    return R == 1 && M % 128 == 0 && (((uintptr_t)a | (uintptr_t)b) & 31) == 0;
+}
+hipError_t launch_couple_rhs(const KArgs& ka, hipStream_t s) {
+    if (gemv2_ok(ka.L.M, ka.R, ka.L.B, ka.L.C)) {
+        hipLaunchKernelGGL(k_couple_rhs_v, dim3(ka.L.P - 1, ka.L.M / RV_ROWS), dim3(256), 0, s, ka);
+        return hipGetLastError();
+    }
+    return launch_gemm<GM_COUPLE_RHS, 1>(ka, ka.L.P - 1, ka.L.M, ka.R, s);
+}
 hipError_t launch_recover(const KArgs& ka, hipStream_t s) {
-    if (ka.R == 1 && ka.L.M % 128 == 0) {
-        hipLaunchKernelGGL((k_recover_v<1>), dim3(ka.L.N), dim3(256), 0, s, ka);
+    if (gemv2_ok(ka.L.M, ka.R, ka.L.Z, ka.L.Z)) {
+        hipLaunchKernelGGL(k_recover_v, dim3(ka.L.N, ka.L.M / RV_ROWS), dim3(256), 0, s, ka);
         return hipGetLastError();
     }
     return launch_gemm<GM_RECOVER, 1>(ka, ka.L.N, ka.L.M, ka.R, s);
