@@ -2536,6 +2536,189 @@ __global__ __launch_bounds__(256) void k_chunk_solve(const KArgs ka) {
     }
 }
 
+// ------------------------------------------------------------------ right-hand-side sweep, one column
+//
+// The sweep of k_chunk_solve for R = 1 and M a multiple of 64, shaped to
+// run beside the factorization's product kernels on the same CUs (at most
+// 128 VGPRs per lane and a few KiB of LDS, where k_chunk_solve's register
+// file and LDS leave no room for another workgroup).  One workgroup per
+// chunk; every step is a set of products of matrix rows with a vector in
+// LDS, 16 lanes per row (four rows per wave instruction) and a DPP sum over
+// the 16 lanes:
+//   forward, row i:  t = P_i (F_i - B_i y_{i-1})   (rows of B_i, F_i taken in pivot order)
+//                    t := L_i^{-1} t   by 32-row blocks: the rows below block b subtract the
+//                                      product of their scaled segment of block b with t_b,
+//                                      then every block takes the inverse of its diagonal
+//                                      block of L
+//                    y_i = U_i^{-1} t  the same upwards with the blocks of U
+//   backward, row i: z_i = y_i - E_i z_{i+1}
+// (the F part of Eq. e231 by the Thomas algorithm of Sec. 3 with the LU
+// factors).  Loads come from clamped addresses in batches, all in flight
+// before the first use.
+
+// Sum over each 16-lane row; every lane of the row holds the row's sum.
+__device__ __forceinline__ double row16_sum(double v) {
+    v += dpp_mov<0xB1>(v);    // quad_perm [1,0,3,2]
+    v += dpp_mov<0x4E>(v);    // quad_perm [2,3,0,1]
+    v += dpp_mov<0x141>(v);   // row_half_mirror
+    v += dpp_mov<0x140>(v);   // row_mirror
+    return v;
+}
+
+constexpr int RS_BATCH = 8;   // passes of 16 rows whose loads are issued together
+
+// Rows q = 16 p + 4 w + g (p < M / 16) of outl (LDS) and outg (global, optional):
+// out[q] = base[s] - Mx[s, :] y with s = pm[q] (PERM) or q, Mx row-major with
+// leading dimension ld (no product unless HASM), y in LDS; lane j covers the
+// columns 4 j + 64 c, c < NPC.
+template <int NPC, bool HASM, bool PERM>
+__device__ __forceinline__ void rs_gemv(const double* __restrict__ Mx, int ld, const int* pm, const double* base,
+                                        const double* y, double* outl, double* outg, int lane, int w) {
+    constexpr int M = 64 * NPC, NP = M / 16;
+    constexpr int PB = NPC >= 4 ? 1 : 4 / NPC;   // passes per batch: 4 double4 loads per lane (NPC above 4: NPC)
+    const int j = lane & 15, g = lane >> 4;
+    for (int p0 = 0; p0 < NP; p0 += PB) {
+        double4 v[PB][NPC];
+        int src[PB];
+        double bs[PB];
+#pragma unroll
+        for (int pb = 0; pb < PB; ++pb) {
+            const int q = 16 * (p0 + pb) + 4 * w + g;
+            src[pb] = PERM ? pm[q] : q;
+        }
+#pragma unroll
+        for (int pb = 0; pb < PB; ++pb) {
+            bs[pb] = base[src[pb]];
+            if constexpr (HASM) {
+#pragma unroll
+                for (int c = 0; c < NPC; ++c) v[pb][c] = *(const double4*)(Mx + (size_t)src[pb] * ld + 4 * j + 64 * c);
+            }
+        }
+#pragma unroll
+        for (int pb = 0; pb < PB; ++pb) {
+            double a = 0.0;
+            if constexpr (HASM) {
+#pragma unroll
+                for (int c = 0; c < NPC; ++c) {
+                    const double4 yv = *(const double4*)(y + 4 * j + 64 * c);
+                    a = fma(v[pb][c].x, yv.x, a);
+                    a = fma(v[pb][c].y, yv.y, a);
+                    a = fma(v[pb][c].z, yv.z, a);
+                    a = fma(v[pb][c].w, yv.w, a);
+                }
+            }
+            a = row16_sum(a);
+            if (j == 0) {
+                const int q = 16 * (p0 + pb) + 4 * w + g;
+                const double r = bs[pb] - a;
+                outl[q] = r;
+                if (outg) outg[q] = r;
+            }
+        }
+    }
+}
+
+// t[r] -= Mx[r, c0 : c0 + 32] t[c0 : c0 + 32] for the rows r = lo + 16 p + 4 w + g,
+// p < np (the rows lie outside [c0, c0 + 32)); lane j covers columns c0 + 2 j, + 1.
+__device__ __forceinline__ void rs_seg(const double* __restrict__ Mx, int ld, int c0, int lo, int np, double* t,
+                                       int lane, int w) {
+    const int j = lane & 15, g = lane >> 4;
+    const double u0 = t[c0 + 2 * j], u1 = t[c0 + 2 * j + 1];
+    for (int p0 = 0; p0 < np; p0 += RS_BATCH) {
+        double2 v[RS_BATCH];
+#pragma unroll
+        for (int pb = 0; pb < RS_BATCH; ++pb) {
+            const int r = lo + 16 * min(p0 + pb, np - 1) + 4 * w + g;
+            v[pb] = *(const double2*)(Mx + (size_t)r * ld + c0 + 2 * j);
+        }
+#pragma unroll
+        for (int pb = 0; pb < RS_BATCH; ++pb) {
+            const double a = row16_sum(fma(v[pb].x, u0, v[pb].y * u1));
+            if (p0 + pb < np && j == 0) t[lo + 16 * (p0 + pb) + 4 * w + g] -= a;
+        }
+    }
+}
+
+// dst[r] = inv(T_b)[r - 32 b, :] t[32 b : 32 b + 32] for every row r < M (b = r / 32),
+// the inverse blocks at di + b * DI_STRIDE + off; also to outg when given.
+__device__ __forceinline__ void rs_diag(const double* __restrict__ di, int off, int M, const double* t, double* dst,
+                                        double* outg, int lane, int w) {
+    const int j = lane & 15, g = lane >> 4;
+    const int np = M / 16;
+    for (int p0 = 0; p0 < np; p0 += RS_BATCH) {
+        double2 v[RS_BATCH];
+#pragma unroll
+        for (int pb = 0; pb < RS_BATCH; ++pb) {
+            const int r = 16 * min(p0 + pb, np - 1) + 4 * w + g;
+            v[pb] = *(const double2*)(di + (size_t)(r >> 5) * DI_STRIDE + off + (r & 31) * DB + 2 * j);
+        }
+#pragma unroll
+        for (int pb = 0; pb < RS_BATCH; ++pb) {
+            const int r = 16 * (p0 + pb) + 4 * w + g, b0 = r & ~31;
+            const double a = row16_sum(fma(v[pb].x, t[b0 + 2 * j], v[pb].y * t[b0 + 2 * j + 1]));
+            if (p0 + pb < np && j == 0) {
+                dst[r] = a;
+                if (outg) outg[r] = a;
+            }
+        }
+    }
+}
+
+template <int NPC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_rhs_sweep1(const KArgs ka) {
+    constexpr int M = 64 * NPC, NBLK = M / DB;
+    const Level& L = ka.L;
+    const int k = blockIdx.x;
+    const int r0 = chunk_first(L, k), e = chunk_last(L, k);
+    if (e < r0) return;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const size_t MM = (size_t)M * M;
+    __shared__ double buf[3][M];
+    __shared__ int pm[M];
+    double* ya = buf[0];   // y of the previous row (z of the next row going back)
+    double* tb = buf[1];   // the row being solved
+    double* t2 = buf[2];
+    constexpr int PU = (M + 255) / 256;
+    int pn[PU];            // the next row's permutation, loaded a row ahead
+#pragma unroll
+    for (int u = 0; u < PU; ++u)
+        if (tid + 256 * u < M) pm[tid + 256 * u] = L.perm[(size_t)r0 * M + tid + 256 * u];
+    __syncthreads();
+    for (int i = r0; i <= e; ++i) {
+        const int inext = min(i + 1, e);
+#pragma unroll
+        for (int u = 0; u < PU; ++u)
+            pn[u] = tid + 256 * u < M ? L.perm[(size_t)inext * M + tid + 256 * u] : 0;
+        const double* LUi = L.LU + i * MM;
+        const double* DIi = L.DI + (size_t)i * NBLK * DI_STRIDE;
+        if (i > r0) rs_gemv<NPC, true, true>(L.B + i * MM, M, pm, ka.F + (size_t)i * M, ya, tb, nullptr, lane, w);
+        else rs_gemv<NPC, false, true>(nullptr, M, pm, ka.F + (size_t)i * M, ya, tb, nullptr, lane, w);
+        __syncthreads();
+        for (int bb = 0; bb + 1 < NBLK; ++bb) {
+            rs_seg(LUi, M, bb * DB, (bb + 1) * DB, (M - (bb + 1) * DB) / 16, tb, lane, w);
+            __syncthreads();
+        }
+        rs_diag(DIi, 0, M, tb, t2, nullptr, lane, w);
+        __syncthreads();
+        for (int bb = NBLK - 1; bb > 0; --bb) {
+            rs_seg(LUi, M, bb * DB, 0, bb * DB / 16, t2, lane, w);
+            __syncthreads();
+        }
+        rs_diag(DIi, DB * DB, M, t2, tb, ka.X + (size_t)i * M, lane, w);
+#pragma unroll
+        for (int u = 0; u < PU; ++u)
+            if (tid + 256 * u < M) pm[tid + 256 * u] = pn[u];
+        __syncthreads();
+        double* sw = ya; ya = tb; tb = sw;
+    }
+    for (int i = e - 1; i >= r0; --i) {
+        double* Xi = ka.X + (size_t)i * M;
+        rs_gemv<NPC, true, false>(L.W + i * MM * 2, 2 * M, nullptr, Xi, ya, tb, Xi, lane, w);
+        __syncthreads();
+        double* sw = ya; ya = tb; tb = sw;
+    }
+}
+
 // ------------------------------------------------------------------ small utility kernels
 
 __global__ void k_init_status(unsigned long long* st) {
@@ -2988,6 +3171,19 @@ static void launch_chunk_solve_kc(const KArgs& ka, int rb, dim3 grid, size_t lds
 
 hipError_t launch_chunk_solve(const KArgs& ka, hipStream_t s) {
     const int M = ka.L.M, rb = chunk_solve_rb(M, ka.R);
+    if (ka.R == 1 && M % 64 == 0 && ((uintptr_t)ka.L.B & 31) == 0) {
+        switch (M / 64) {
+            case 1: hipLaunchKernelGGL(k_rhs_sweep1<1>, dim3(ka.L.P), dim3(256), 0, s, ka); break;
+            case 2: hipLaunchKernelGGL(k_rhs_sweep1<2>, dim3(ka.L.P), dim3(256), 0, s, ka); break;
+            case 3: hipLaunchKernelGGL(k_rhs_sweep1<3>, dim3(ka.L.P), dim3(256), 0, s, ka); break;
+            case 4: hipLaunchKernelGGL(k_rhs_sweep1<4>, dim3(ka.L.P), dim3(256), 0, s, ka); break;
+            case 5: hipLaunchKernelGGL(k_rhs_sweep1<5>, dim3(ka.L.P), dim3(256), 0, s, ka); break;
+            case 6: hipLaunchKernelGGL(k_rhs_sweep1<6>, dim3(ka.L.P), dim3(256), 0, s, ka); break;
+            case 7: hipLaunchKernelGGL(k_rhs_sweep1<7>, dim3(ka.L.P), dim3(256), 0, s, ka); break;
+            default: hipLaunchKernelGGL(k_rhs_sweep1<8>, dim3(ka.L.P), dim3(256), 0, s, ka); break;
+        }
+        return hipGetLastError();
+    }
     dim3 grid(ka.L.P, cdiv(ka.R, rb));
     const size_t lds = chunk_solve_lds_bytes(M, ka.R);
     if (chunk_solve_kc(M) == 32) launch_chunk_solve_kc<32>(ka, rb, grid, lds, s);

@@ -75,7 +75,8 @@ def test_small_workload(P, depth):
     (40, 33, 5, 6, 1), (21, 65, 33, 4, 0), (30, 100, 2, 7, 1), (9, 129, 65, 3, 0), (12, 64, 64, 4, 0),
     (25, 31, 7, 12, 1), (9, 257, 3, 3, 1), (6, 300, 20, 2, 0), (10, 256, 1, 4, 0),
     (20, 130, 3, 4, 1), (30, 6, 2, 5, 0), (11, 130, 20, 3, 0), (17, 2, 5, 4, 1),
-    (7, 512, 1, 3, 0), (9, 384, 1, 4, 1), (12, 128, 1, 5, 1),
+    (7, 512, 1, 3, 0), (9, 384, 1, 4, 1), (12, 128, 1, 5, 1), (20, 64, 1, 4, 1), (15, 192, 1, 3, 0),
+    (8, 320, 1, 2, 0), (6, 448, 1, 2, 0),
 ])
 def test_ragged_shapes(N, M, R, P, depth):
     torch = require_gpu()
