@@ -2249,9 +2249,13 @@ __device__ __forceinline__ void tseq_run2(typename Acc4<CT>::type (&x)[NBLK][2][
 // RHS: the right-hand-side sweep's X_i (R columns, in place) instead of
 // W_i = [C_i | -B_i Y_{i-1}].  CT: product type (float: FP32 MFMA with FP32
 // accumulation on the FP64 factors and right-hand side, for the
-// reduced-precision factor; results stored in FP64).
-template <int NBLK, int NT16, int WPB, bool RHS = false, class CT = double>
-__global__ __launch_bounds__(64 * WPB) void k_getrs_s(const KArgs ka, int nslab, int wpc) {
+// reduced-precision factor; results stored in FP64).  WPE: waves per SIMD
+// the register allocation must admit (2: at most 256 VGPRs, so that two
+// four-wave workgroups share a CU and one's barriers are covered by the
+// other's products).
+template <int NBLK, int NT16, int WPB, bool RHS = false, class CT = double, int WPE = 1>
+__global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE))) void k_getrs_s(const KArgs ka,
+                                                                                                  int nslab, int wpc) {
     typedef typename Acc4<CT>::type V4;
     __shared__ CT ring[TS_RING * TS_BLOCK];
     const Level& L = ka.L;
@@ -3101,20 +3105,21 @@ hipError_t launch_diag_inv(const KArgs& ka, hipStream_t s) {
 
 static int slab_width(int M) { return M <= 256 ? 32 : 16; }
 
-template <int NBLK, int NT16, int WPB = 4, bool RHS = false>
+template <int NBLK, int NT16, int WPB = 4, bool RHS = false, int WPE = 1>
 static void launch_getrs_s(const KArgs& ka, hipStream_t s) {
     const int nslab = cdiv(RHS ? ka.R : 2 * ka.L.M, 16 * NT16), wpc = cdiv(nslab, WPB);
     if (!RHS && ka.lowp)
-        hipLaunchKernelGGL((k_getrs_s<NBLK, NT16, WPB, false, float>), dim3(wpc * ka.nc), dim3(64 * WPB), 0, s, ka,
-                           nslab, wpc);
+        hipLaunchKernelGGL((k_getrs_s<NBLK, NT16, WPB, false, float, WPE>), dim3(wpc * ka.nc), dim3(64 * WPB), 0, s,
+                           ka, nslab, wpc);
     else
-        hipLaunchKernelGGL((k_getrs_s<NBLK, NT16, WPB, RHS>), dim3(wpc * ka.nc), dim3(64 * WPB), 0, s, ka, nslab, wpc);
+        hipLaunchKernelGGL((k_getrs_s<NBLK, NT16, WPB, RHS, double, WPE>), dim3(wpc * ka.nc), dim3(64 * WPB), 0, s,
+                           ka, nslab, wpc);
 }
 
-// M <= 256: slabs of 32 columns (64 for M <= 64; 16 above M = 128, so that
-// two waves fit on a SIMD) held in one wave's accumulators, four slabs of
-// one chunk per workgroup (eight above M = 128) sharing the factor blocks
-// through LDS; above: the workgroup slab kernel.
+// M <= 256: slabs of 32 columns (64 for M <= 64; 16 above M = 128) held in
+// one wave's accumulators, four slabs of one chunk per workgroup sharing the
+// factor blocks through LDS (above M = 128 with at most 256 VGPRs, two
+// workgroups per CU); above: the workgroup slab kernel.
 hipError_t launch_getrs(const KArgs& ka, hipStream_t s) {
     const int M = ka.L.M;
     if (M <= 256) {
@@ -3122,7 +3127,7 @@ hipError_t launch_getrs(const KArgs& ka, hipStream_t s) {
         if (nblk <= 1) launch_getrs_s<1, 4>(ka, s);
         else if (nblk <= 2) launch_getrs_s<2, 4>(ka, s);
         else if (nblk <= 4) launch_getrs_s<4, 2>(ka, s);
-        else launch_getrs_s<8, 1, 8>(ka, s);   // 16-column slabs: two waves per SIMD
+        else launch_getrs_s<8, 1, 4, false, 2>(ka, s);
         return hipGetLastError();
     }
     const int sw = slab_width(M);
