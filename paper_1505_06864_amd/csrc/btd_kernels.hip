@@ -2551,14 +2551,18 @@ __global__ __launch_bounds__(256) void k_chunk_solve(const KArgs ka) {
 // the 16 lanes:
 //   forward, row i:  t = P_i (F_i - B_i y_{i-1})   (rows of B_i, F_i taken in pivot order)
 //                    t := L_i^{-1} t   by 32-row blocks: the rows below block b subtract the
-//                                      product of their scaled segment of block b with t_b,
+//                                      product of their (scaled) segment of block b with t_b,
 //                                      then every block takes the inverse of its diagonal
 //                                      block of L
 //                    y_i = U_i^{-1} t  the same upwards with the blocks of U
 //   backward, row i: z_i = y_i - E_i z_{i+1}
 // (the F part of Eq. e231 by the Thomas algorithm of Sec. 3 with the LU
-// factors).  Loads come from clamped addresses in batches, all in flight
-// before the first use.
+// factors).  The kernel is bound by load latency (one workgroup per chunk),
+// so its loads run two batches ahead: a batch's products are formed, the
+// batch after next is loaded into the same registers, then the sums are
+// reduced and written; the factor loads do not depend on the vector, so
+// they cross the barriers between steps.  Loads come from clamped
+// addresses, unconditionally.
 
 // Sum over each 16-lane row; every lane of the row holds the row's sum.
 __device__ __forceinline__ double row16_sum(double v) {
@@ -2569,52 +2573,177 @@ __device__ __forceinline__ double row16_sum(double v) {
     return v;
 }
 
-constexpr int RS_BATCH = 8;   // passes of 16 rows whose loads are issued together
+constexpr int RS_BATCH = 8;   // passes of 16 rows per batch of the triangular solve
+
+// Streaming loads of the factors (non-temporal: the sweep reads each value
+// once, and runs beside product kernels whose operands live in L2).
+typedef double v2d __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double2 ld_stream2(const double* p) {
+    const v2d v = __builtin_nontemporal_load((const v2d*)p);
+    return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ double4 ld_stream4(const double* p) {
+    const v4d v = __builtin_nontemporal_load((const v4d*)p);
+    return make_double4(v.x, v.y, v.z, v.w);
+}
+
+// One batch of the triangular solve of a row: kind 0 a step of L (block bb,
+// the rows below it), 1 the diagonal blocks of L, 2 a step of U (block bb,
+// the rows above it), 3 the diagonal blocks of U; passes p0 .. p0 + 7 of np;
+// `last`: the last batch of its step (a barrier follows).
+struct RsUnit {
+    int kind, bb, p0, np;
+    bool last;
+};
+
+template <int NBLK>
+struct RsPlan {
+    static constexpr int nb(int np) { return (np + RS_BATCH - 1) / RS_BATCH; }
+    static constexpr int count() {
+        int n = 0;
+        for (int bb = 0; bb + 1 < NBLK; ++bb) n += nb(2 * (NBLK - 1 - bb));
+        n += nb(2 * NBLK);
+        for (int bb = NBLK - 1; bb > 0; --bb) n += nb(2 * bb);
+        return n + nb(2 * NBLK);
+    }
+    static constexpr RsUnit unit(int want) {
+        int n = 0;
+        for (int ph = 0; ph < 4; ++ph) {
+            const int steps = (ph == 1 || ph == 3) ? 1 : NBLK - 1;
+            for (int s = 0; s < steps; ++s) {
+                const int bb = ph == 0 ? s : ph == 2 ? NBLK - 1 - s : 0;
+                const int np = ph == 0 ? 2 * (NBLK - 1 - bb) : ph == 2 ? 2 * bb : 2 * NBLK;
+                for (int q = 0; q < nb(np); ++q, ++n)
+                    if (n == want) return RsUnit{ph, bb, q * RS_BATCH, np, q + 1 == nb(np)};
+            }
+        }
+        return RsUnit{-1, 0, 0, 0, false};
+    }
+};
+
+// Row of pass p of a unit for this lane's row group.
+__device__ __forceinline__ int rs_row(const RsUnit& u, int p, int w, int g) {
+    const int lo = u.kind == 0 ? DB * (u.bb + 1) : 0;
+    return lo + 16 * p + 4 * w + g;
+}
+
+template <int NBLK, int N>
+__device__ __forceinline__ void rs_load(double2 (&v)[RS_BATCH], const double* __restrict__ lu,
+                                        const double* __restrict__ di, int lane, int w) {
+    constexpr int M = NBLK * DB;
+    constexpr RsUnit u = RsPlan<NBLK>::unit(N);
+    if constexpr (u.kind >= 0) {
+        // the lane's indices made opaque per batch: addresses are formed at
+        // the loads instead of for every batch up front (registers)
+        int lo = lane, wo = w;
+        __asm__ volatile("" : "+v"(lo), "+v"(wo));
+        const int j = lo & 15, g = lo >> 4;
+        w = wo;
+#pragma unroll
+        for (int pb = 0; pb < RS_BATCH; ++pb) {
+            const int r = rs_row(u, min(u.p0 + pb, u.np - 1), w, g);
+            if constexpr (u.kind == 0 || u.kind == 2)
+                v[pb] = ld_stream2(lu + (size_t)r * M + DB * u.bb + 2 * j);
+            else
+                v[pb] = ld_stream2(di + (size_t)(r >> 5) * DI_STRIDE + (u.kind == 3 ? DB * DB : 0) + (r & 31) * DB +
+                                   2 * j);
+        }
+    }
+}
+
+// Unit N from va; unit N + 2 is loaded into va once its products are
+// formed; then N + 1 from vb.  The vector is in ta (L steps, the diagonal
+// of L reads ta and writes tc; U steps in tc, the diagonal of U reads tc
+// and writes ta and the row of X).
+template <int NBLK, int N>
+__device__ __forceinline__ void rs_run(double2 (&va)[RS_BATCH], double2 (&vb)[RS_BATCH], const double* __restrict__ lu,
+                                       const double* __restrict__ di, double* ta, double* tc, double* xg, int lane,
+                                       int w) {
+    constexpr int NU = RsPlan<NBLK>::count();
+    if constexpr (N < NU) {
+        constexpr RsUnit u = RsPlan<NBLK>::unit(N);
+        int lo = lane, wo = w;
+        __asm__ volatile("" : "+v"(lo), "+v"(wo));
+        const int j = lo & 15, g = lo >> 4;
+        double part[RS_BATCH];
+        if constexpr (u.kind == 0 || u.kind == 2) {
+            const double* t = u.kind == 0 ? ta : tc;
+            const double u0 = t[DB * u.bb + 2 * j], u1 = t[DB * u.bb + 2 * j + 1];
+#pragma unroll
+            for (int pb = 0; pb < RS_BATCH; ++pb) part[pb] = fma(va[pb].x, u0, va[pb].y * u1);
+        } else {
+            const double* t = u.kind == 1 ? ta : tc;
+#pragma unroll
+            for (int pb = 0; pb < RS_BATCH; ++pb) {
+                const int b0 = rs_row(u, u.p0 + pb, wo, g) & ~31;
+                part[pb] = fma(va[pb].x, t[b0 + 2 * j], va[pb].y * t[b0 + 2 * j + 1]);
+            }
+        }
+        rs_load<NBLK, N + 2>(va, lu, di, lane, w);
+#pragma unroll
+        for (int pb = 0; pb < RS_BATCH; ++pb) {
+            const double a = row16_sum(part[pb]);
+            if (u.p0 + pb < u.np && j == 0) {
+                const int r = rs_row(u, u.p0 + pb, wo, g);
+                if constexpr (u.kind == 0) ta[r] -= a;
+                else if constexpr (u.kind == 2) tc[r] -= a;
+                else if constexpr (u.kind == 1) tc[r] = a;
+                else {
+                    ta[r] = a;
+                    xg[r] = a;
+                }
+            }
+        }
+        if constexpr (u.last) __syncthreads();
+        rs_run<NBLK, N + 1>(vb, va, lu, di, ta, tc, xg, lane, w);
+    }
+}
 
 // Rows q = 16 p + 4 w + g (p < M / 16) of outl (LDS) and outg (global, optional):
 // out[q] = base[s] - Mx[s, :] y with s = pm[q] (PERM) or q, Mx row-major with
 // leading dimension ld (no product unless HASM), y in LDS; lane j covers the
-// columns 4 j + 64 c, c < NPC.
+// columns 4 j + 64 c, c < NPC.  Up to M = 256 two passes are in flight (the
+// pass after next loaded once a pass's products are formed).
 template <int NPC, bool HASM, bool PERM>
 __device__ __forceinline__ void rs_gemv(const double* __restrict__ Mx, int ld, const int* pm, const double* base,
                                         const double* y, double* outl, double* outg, int lane, int w) {
     constexpr int M = 64 * NPC, NP = M / 16;
-    constexpr int PB = NPC >= 4 ? 1 : 4 / NPC;   // passes per batch: 4 double4 loads per lane (NPC above 4: NPC)
+    constexpr int AHEAD = NPC <= 4 ? 2 : 1;
     const int j = lane & 15, g = lane >> 4;
-    for (int p0 = 0; p0 < NP; p0 += PB) {
-        double4 v[PB][NPC];
-        int src[PB];
-        double bs[PB];
+    double4 v[AHEAD][HASM ? NPC : 1];
+    double bs[AHEAD];
+    auto load = [&](int p, double4 (&d)[HASM ? NPC : 1], double& b) {
+        const int q = 16 * min(p, NP - 1) + 4 * w + g;
+        const int sr = PERM ? pm[q] : q;
+        b = base[sr];
+        if constexpr (HASM) {
 #pragma unroll
-        for (int pb = 0; pb < PB; ++pb) {
-            const int q = 16 * (p0 + pb) + 4 * w + g;
-            src[pb] = PERM ? pm[q] : q;
+            for (int c = 0; c < NPC; ++c) d[c] = ld_stream4(Mx + (size_t)sr * ld + 4 * j + 64 * c);
         }
+    };
 #pragma unroll
-        for (int pb = 0; pb < PB; ++pb) {
-            bs[pb] = base[src[pb]];
-            if constexpr (HASM) {
+    for (int k = 0; k < AHEAD; ++k) load(k, v[k], bs[k]);
+    for (int p0 = 0; p0 < NP; p0 += AHEAD) {
 #pragma unroll
-                for (int c = 0; c < NPC; ++c) v[pb][c] = *(const double4*)(Mx + (size_t)src[pb] * ld + 4 * j + 64 * c);
-            }
-        }
-#pragma unroll
-        for (int pb = 0; pb < PB; ++pb) {
+        for (int k = 0; k < AHEAD; ++k) {
+            const int p = p0 + k;
             double a = 0.0;
             if constexpr (HASM) {
 #pragma unroll
                 for (int c = 0; c < NPC; ++c) {
                     const double4 yv = *(const double4*)(y + 4 * j + 64 * c);
-                    a = fma(v[pb][c].x, yv.x, a);
-                    a = fma(v[pb][c].y, yv.y, a);
-                    a = fma(v[pb][c].z, yv.z, a);
-                    a = fma(v[pb][c].w, yv.w, a);
+                    a = fma(v[k][c].x, yv.x, a);
+                    a = fma(v[k][c].y, yv.y, a);
+                    a = fma(v[k][c].z, yv.z, a);
+                    a = fma(v[k][c].w, yv.w, a);
                 }
             }
+            const double b = bs[k];
+            load(p + AHEAD, v[k], bs[k]);
             a = row16_sum(a);
             if (j == 0) {
-                const int q = 16 * (p0 + pb) + 4 * w + g;
-                const double r = bs[pb] - a;
+                const int q = 16 * p + 4 * w + g;
+                const double r = b - a;
                 outl[q] = r;
                 if (outg) outg[q] = r;
             }
@@ -2622,61 +2751,46 @@ __device__ __forceinline__ void rs_gemv(const double* __restrict__ Mx, int ld, c
     }
 }
 
-// t[r] -= Mx[r, c0 : c0 + 32] t[c0 : c0 + 32] for the rows r = lo + 16 p + 4 w + g,
-// p < np (the rows lie outside [c0, c0 + 32)); lane j covers columns c0 + 2 j, + 1.
-__device__ __forceinline__ void rs_seg(const double* __restrict__ Mx, int ld, int c0, int lo, int np, double* t,
-                                       int lane, int w) {
-    const int j = lane & 15, g = lane >> 4;
-    const double u0 = t[c0 + 2 * j], u1 = t[c0 + 2 * j + 1];
-    for (int p0 = 0; p0 < np; p0 += RS_BATCH) {
-        double2 v[RS_BATCH];
-#pragma unroll
-        for (int pb = 0; pb < RS_BATCH; ++pb) {
-            const int r = lo + 16 * min(p0 + pb, np - 1) + 4 * w + g;
-            v[pb] = *(const double2*)(Mx + (size_t)r * ld + c0 + 2 * j);
-        }
-#pragma unroll
-        for (int pb = 0; pb < RS_BATCH; ++pb) {
-            const double a = row16_sum(fma(v[pb].x, u0, v[pb].y * u1));
-            if (p0 + pb < np && j == 0) t[lo + 16 * (p0 + pb) + 4 * w + g] -= a;
-        }
-    }
+// Forward row i of a chunk (first row r0): pm holds P_i, ya y_{i-1}; the
+// solution goes to tb and X_i.
+template <int NPC>
+__device__ __forceinline__ void rs_forward_row(const KArgs& ka, int i, int r0, const int* pm, const double* ya,
+                                               double* tb, double* t2, int lane, int w) {
+    constexpr int M = 64 * NPC, NBLK = M / DB;
+    const Level& L = ka.L;
+    const size_t MM = (size_t)M * M;
+    const double* LUi = L.LU + i * MM;
+    const double* DIi = L.DI + (size_t)i * NBLK * DI_STRIDE;
+    if (i > r0) rs_gemv<NPC, true, true>(L.B + i * MM, M, pm, ka.F + (size_t)i * M, ya, tb, nullptr, lane, w);
+    else rs_gemv<NPC, false, true>(nullptr, M, pm, ka.F + (size_t)i * M, ya, tb, nullptr, lane, w);
+    double2 va[RS_BATCH], vb[RS_BATCH];
+    rs_load<NBLK, 0>(va, LUi, DIi, lane, w);
+    rs_load<NBLK, 1>(vb, LUi, DIi, lane, w);
+    __syncthreads();
+    rs_run<NBLK, 0>(va, vb, LUi, DIi, tb, t2, ka.X + (size_t)i * M, lane, w);
 }
 
-// dst[r] = inv(T_b)[r - 32 b, :] t[32 b : 32 b + 32] for every row r < M (b = r / 32),
-// the inverse blocks at di + b * DI_STRIDE + off; also to outg when given.
-__device__ __forceinline__ void rs_diag(const double* __restrict__ di, int off, int M, const double* t, double* dst,
-                                        double* outg, int lane, int w) {
-    const int j = lane & 15, g = lane >> 4;
-    const int np = M / 16;
-    for (int p0 = 0; p0 < np; p0 += RS_BATCH) {
-        double2 v[RS_BATCH];
-#pragma unroll
-        for (int pb = 0; pb < RS_BATCH; ++pb) {
-            const int r = 16 * min(p0 + pb, np - 1) + 4 * w + g;
-            v[pb] = *(const double2*)(di + (size_t)(r >> 5) * DI_STRIDE + off + (r & 31) * DB + 2 * j);
-        }
-#pragma unroll
-        for (int pb = 0; pb < RS_BATCH; ++pb) {
-            const int r = 16 * (p0 + pb) + 4 * w + g, b0 = r & ~31;
-            const double a = row16_sum(fma(v[pb].x, t[b0 + 2 * j], v[pb].y * t[b0 + 2 * j + 1]));
-            if (p0 + pb < np && j == 0) {
-                dst[r] = a;
-                if (outg) outg[r] = a;
-            }
-        }
+// Backward rows e-1 .. r0 of a chunk: ya holds z_e on entry.
+template <int NPC>
+__device__ __forceinline__ void rs_backward(const KArgs& ka, int r0, int e, double* ya, double* tb, int lane, int w) {
+    constexpr int M = 64 * NPC;
+    const size_t MM = (size_t)M * M;
+    for (int i = e - 1; i >= r0; --i) {
+        double* Xi = ka.X + (size_t)i * M;
+        rs_gemv<NPC, true, false>(ka.L.W + i * MM * 2, 2 * M, nullptr, Xi, ya, tb, Xi, lane, w);
+        __syncthreads();
+        double* sw = ya; ya = tb; tb = sw;
     }
 }
 
 template <int NPC>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_rhs_sweep1(const KArgs ka) {
-    constexpr int M = 64 * NPC, NBLK = M / DB;
+    constexpr int M = 64 * NPC;
     const Level& L = ka.L;
     const int k = blockIdx.x;
     const int r0 = chunk_first(L, k), e = chunk_last(L, k);
     if (e < r0) return;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const size_t MM = (size_t)M * M;
     __shared__ double buf[3][M];
     __shared__ int pm[M];
     double* ya = buf[0];   // y of the previous row (z of the next row going back)
@@ -2693,34 +2807,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 #pragma unroll
         for (int u = 0; u < PU; ++u)
             pn[u] = tid + 256 * u < M ? L.perm[(size_t)inext * M + tid + 256 * u] : 0;
-        const double* LUi = L.LU + i * MM;
-        const double* DIi = L.DI + (size_t)i * NBLK * DI_STRIDE;
-        if (i > r0) rs_gemv<NPC, true, true>(L.B + i * MM, M, pm, ka.F + (size_t)i * M, ya, tb, nullptr, lane, w);
-        else rs_gemv<NPC, false, true>(nullptr, M, pm, ka.F + (size_t)i * M, ya, tb, nullptr, lane, w);
-        __syncthreads();
-        for (int bb = 0; bb + 1 < NBLK; ++bb) {
-            rs_seg(LUi, M, bb * DB, (bb + 1) * DB, (M - (bb + 1) * DB) / 16, tb, lane, w);
-            __syncthreads();
-        }
-        rs_diag(DIi, 0, M, tb, t2, nullptr, lane, w);
-        __syncthreads();
-        for (int bb = NBLK - 1; bb > 0; --bb) {
-            rs_seg(LUi, M, bb * DB, 0, bb * DB / 16, t2, lane, w);
-            __syncthreads();
-        }
-        rs_diag(DIi, DB * DB, M, t2, tb, ka.X + (size_t)i * M, lane, w);
+        rs_forward_row<NPC>(ka, i, r0, pm, ya, tb, t2, lane, w);
 #pragma unroll
         for (int u = 0; u < PU; ++u)
             if (tid + 256 * u < M) pm[tid + 256 * u] = pn[u];
         __syncthreads();
         double* sw = ya; ya = tb; tb = sw;
     }
-    for (int i = e - 1; i >= r0; --i) {
-        double* Xi = ka.X + (size_t)i * M;
-        rs_gemv<NPC, true, false>(L.W + i * MM * 2, 2 * M, nullptr, Xi, ya, tb, Xi, lane, w);
-        __syncthreads();
-        double* sw = ya; ya = tb; tb = sw;
-    }
+    rs_backward<NPC>(ka, r0, e, ya, tb, lane, w);
 }
 
 // ------------------------------------------------------------------ small utility kernels
@@ -3174,19 +3268,27 @@ static void launch_chunk_solve_kc(const KArgs& ka, int rb, dim3 grid, size_t lds
     }
 }
 
+// The one-column sweep kernel: R = 1, M a multiple of 64, rows of B 32-byte aligned.
+static bool rhs_lean(int M, int R, const void* B) { return R == 1 && M % 64 == 0 && ((uintptr_t)B & 31) == 0; }
+
+static void launch_rhs_sweep1(const KArgs& ka, hipStream_t s) {
+    const dim3 grid(ka.L.P), block(256);
+    switch (ka.L.M / 64) {
+        case 1: hipLaunchKernelGGL(k_rhs_sweep1<1>, grid, block, 0, s, ka); break;
+        case 2: hipLaunchKernelGGL(k_rhs_sweep1<2>, grid, block, 0, s, ka); break;
+        case 3: hipLaunchKernelGGL(k_rhs_sweep1<3>, grid, block, 0, s, ka); break;
+        case 4: hipLaunchKernelGGL(k_rhs_sweep1<4>, grid, block, 0, s, ka); break;
+        case 5: hipLaunchKernelGGL(k_rhs_sweep1<5>, grid, block, 0, s, ka); break;
+        case 6: hipLaunchKernelGGL(k_rhs_sweep1<6>, grid, block, 0, s, ka); break;
+        case 7: hipLaunchKernelGGL(k_rhs_sweep1<7>, grid, block, 0, s, ka); break;
+        default: hipLaunchKernelGGL(k_rhs_sweep1<8>, grid, block, 0, s, ka); break;
+    }
+}
+
 hipError_t launch_chunk_solve(const KArgs& ka, hipStream_t s) {
     const int M = ka.L.M, rb = chunk_solve_rb(M, ka.R);
-    if (ka.R == 1 && M % 64 == 0 && ((uintptr_t)ka.L.B & 31) == 0) {
-        switch (M / 64) {
-            case 1: hipLaunchKernelGGL(k_rhs_sweep1<1>, dim3(ka.L.P), dim3(256), 0, s, ka); break;
-            case 2: hipLaunchKernelGGL(k_rhs_sweep1<2>, dim3(ka.L.P), dim3(256), 0, s, ka); break;
-            case 3: hipLaunchKernelGGL(k_rhs_sweep1<3>, dim3(ka.L.P), dim3(256), 0, s, ka); break;
-            case 4: hipLaunchKernelGGL(k_rhs_sweep1<4>, dim3(ka.L.P), dim3(256), 0, s, ka); break;
-            case 5: hipLaunchKernelGGL(k_rhs_sweep1<5>, dim3(ka.L.P), dim3(256), 0, s, ka); break;
-            case 6: hipLaunchKernelGGL(k_rhs_sweep1<6>, dim3(ka.L.P), dim3(256), 0, s, ka); break;
-            case 7: hipLaunchKernelGGL(k_rhs_sweep1<7>, dim3(ka.L.P), dim3(256), 0, s, ka); break;
-            default: hipLaunchKernelGGL(k_rhs_sweep1<8>, dim3(ka.L.P), dim3(256), 0, s, ka); break;
-        }
+    if (rhs_lean(ka.L.M, ka.R, ka.L.B)) {
+        launch_rhs_sweep1(ka, s);
         return hipGetLastError();
     }
     dim3 grid(ka.L.P, cdiv(ka.R, rb));
