@@ -1260,6 +1260,40 @@ __device__ __forceinline__ void np_tiles(const double* __restrict__ src, double*
     }
 }
 
+// The 2 x 2 tiles (t, u), (t, u+1), (t+1, u), (t+1, u+1) of the trailing
+// matrix: A22 -= L21 U12 with each K slice's two L21 and two U12 operands
+// read once for four products.
+__device__ __forceinline__ void np_block(const double* __restrict__ src, double* __restrict__ out, int M, int j0,
+                                         int g, int cc, const double* LP, const double* UP, int t, int u) {
+    constexpr int LPP = NP_LPP, UPP = NP_UPP;
+    const double* cbase = src + (size_t)(j0 + NP_NB) * M + j0 + NP_NB;
+    double* obase = out + (size_t)(j0 + NP_NB) * M + j0 + NP_NB;
+    v4d c[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) c[a][b][v] = cbase[(size_t)(16 * (t + a) + g + 4 * v) * M + 16 * (u + b) + cc];
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) {
+        const double a0 = -LP[(16 * t + cc) * LPP + 4 * kk + g];
+        const double a1 = -LP[(16 * (t + 1) + cc) * LPP + 4 * kk + g];
+        const double b0 = UP[(4 * kk + g) * UPP + 16 * u + cc];
+        const double b1 = UP[(4 * kk + g) * UPP + 16 * (u + 1) + cc];
+        c[0][0] = mfma4(a0, b0, c[0][0]);
+        c[0][1] = mfma4(a0, b1, c[0][1]);
+        c[1][0] = mfma4(a1, b0, c[1][0]);
+        c[1][1] = mfma4(a1, b1, c[1][1]);
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) obase[(size_t)(16 * (t + a) + g + 4 * v) * M + 16 * (u + b) + cc] = c[a][b][v];
+}
+
 // The no-interchange factorisation of one block; false (nothing but out
 // written) when a check fails.  Called by all threads of the LU workgroup.
 __device__ __forceinline__ bool getrf_nointerchange(const double* __restrict__ a, double* __restrict__ out, int* __restrict__ perm,
@@ -1306,13 +1340,26 @@ __device__ __forceinline__ bool getrf_nointerchange(const double* __restrict__ a
             // (rows) of its block before it overwrites them (in place from the
             // second panel on), so no two tasks share a block
             bool okp = true;
+            // a task's eight operands per lane: a row piece of A21 (q < nt2) or
+            // a column piece of A12, addressed without a branch; the next
+            // task's operands are loaded before the current task's products
+            // (past the last task: the last one again, unused)
+            auto tload = [&](int q, double (&x)[8]) {
+                const bool lt = q < nt2;
+                const double* base = lt ? src + (size_t)(j0 + NP_NB + 16 * q + cc) * M + j0 + g
+                                        : src + (size_t)(j0 + g) * M + j0 + NP_NB + 16 * (q - nt2) + cc;
+                const size_t st = lt ? 4 : (size_t)4 * M;
+#pragma unroll
+                for (int kk = 0; kk < 8; ++kk) x[kk] = base[kk * st];
+            };
+            double xv[8];
+            if (w < 2 * nt2) tload(w, xv);
             for (int q = w; q < 2 * nt2; q += NW) {
+                double xn[8];
+                tload(min(q + NW, 2 * nt2 - 1), xn);
                 v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
                 if (q < nt2) {
-                    const double* arow = src + (size_t)(j0 + NP_NB + 16 * q + cc) * M + j0 + g;
-                    double av[8];
-#pragma unroll
-                    for (int kk = 0; kk < 8; ++kk) av[kk] = arow[4 * kk];
+                    const double* av = xv;
 #pragma unroll
                     for (int kk = 0; kk < 8; ++kk) {
                         acc0 = mfma4(av[kk], IU[(4 * kk + g) * TP + cc], acc0);
@@ -1330,10 +1377,7 @@ __device__ __forceinline__ bool getrf_nointerchange(const double* __restrict__ a
                     }
                 } else {
                     const int u = q - nt2;
-                    const double* bcol = src + (size_t)(j0 + g) * M + j0 + NP_NB + 16 * u + cc;
-                    double bv[8];
-#pragma unroll
-                    for (int kk = 0; kk < 8; ++kk) bv[kk] = bcol[(size_t)4 * kk * M];
+                    const double* bv = xv;
 #pragma unroll
                     for (int kk = 0; kk < 8; ++kk) {
                         acc0 = mfma4(IL[cc * TP + 4 * kk + g], bv[kk], acc0);
@@ -1348,6 +1392,8 @@ __device__ __forceinline__ bool getrf_nointerchange(const double* __restrict__ a
                         UP[(16 + row) * UPP + col] = acc1[v];
                     }
                 }
+#pragma unroll
+                for (int kk = 0; kk < 8; ++kk) xv[kk] = xn[kk];
             }
             if (__ballot(!okp) != 0ull && lane == 0) FL[0] = 1;
             __syncthreads();
@@ -1365,18 +1411,13 @@ __device__ __forceinline__ bool getrf_nointerchange(const double* __restrict__ a
             const bool ok = np_diag(j0 < 0 ? a : out, out, M, j0 + NP_NB, T, F, IL, IU, DS, lane);
             if (__ballot(!ok) != 0ull && lane == 0) FL[0] = 1;
         } else if (j0 >= 0) {
-            // the other tiles: rows 0-1 right of the block, then rows 2..
-            const int w1 = nt2 - 2, nr = nt2 * nt2 - 4;
-            auto tile_of = [&](int k, int& t, int& u) {
-                if (k < 2 * w1) { t = k / w1; u = 2 + k - t * w1; }
-                else { const int k2 = k - 2 * w1; t = 2 + k2 / nt2; u = k2 - (t - 2) * nt2; }
-            };
-            for (int k0 = w - 1; k0 < nr; k0 += 2 * (NW - 1)) {
-                const int k1 = min(k0 + NW - 1, nr - 1);   // the second tile (the first again past the end, unused)
-                int t0, u0, t1, u1;
-                tile_of(k0, t0, u0);
-                tile_of(k1, t1, u1);
-                np_tiles(src, out, M, j0, g, cc, LP, UP, t0, u0, t1, u1, k0 + NW - 1 < nr);
+            // the other tiles in 2 x 2 blocks (the block of the next diagonal
+            // block excluded): two row operands and two column operands from
+            // LDS feed four products per K slice
+            const int nb2 = nt2 / 2;
+            for (int kb = w; kb < nb2 * nb2; kb += NW - 1) {
+                const int bt = kb / nb2, bu = kb - bt * nb2;
+                np_block(src, out, M, j0, g, cc, LP, UP, 2 * bt, 2 * bu);
             }
         }
         __syncthreads();
