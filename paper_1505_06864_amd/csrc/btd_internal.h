@@ -54,6 +54,10 @@ hipError_t launch_couple(const KArgs& ka, hipStream_t s);
 hipError_t launch_couple_rhs(const KArgs& ka, hipStream_t s);
 hipError_t launch_recover(const KArgs& ka, hipStream_t s);
 hipError_t launch_getrf(const KArgs& ka, hipStream_t s);
+// The LU kernel prepares its rows for the blocked triangular solves itself
+// (inverses of the diagonal blocks into DI, off-diagonal blocks scaled) when
+// M is a multiple of 32 and at most 256; otherwise launch_diag_inv does.
+bool lu_prepares(int M);
 hipError_t launch_diag_inv(const KArgs& ka, hipStream_t s);
 hipError_t launch_getrs(const KArgs& ka, hipStream_t s);
 hipError_t launch_chunk_solve(const KArgs& ka, hipStream_t s);

@@ -1053,6 +1053,12 @@ __device__ __forceinline__ void lw_panel_steps(double (&v)[4][LW_NB], bool (&act
 //      column, the two off-diagonal blocks on MFMA);
 //   P  L21 = A21 inv(U11) and U12 = inv(L11) A12 on MFMA (all waves);
 //   U  A22 -= L21 U12 on MFMA, two 16 x 16 tiles per wave at a time.
+// It also leaves the factors prepared for the blocked triangular solves
+// (what k_diag_prep does otherwise): inv(L11) and inv(U11) of every
+// diagonal block into DI, the blocks below each diagonal block stored as
+// L21 inv(L11) (one more product per panel task, L21 read back from LDS)
+// and those above it as U12 inv(U11) (panel tasks of the next iteration,
+// and of a last pass for the last block).
 // Every pivot is checked to be finite and non-zero and every multiplier
 // to satisfy |l| <= 1; if any check fails the factorisation is abandoned
 // and the block is factored with interchanges from its unchanged working
@@ -1296,8 +1302,46 @@ __device__ __forceinline__ void np_block(const double* __restrict__ src, double*
 
 // The no-interchange factorisation of one block; false (nothing but out
 // written) when a check fails.  Called by all threads of the LU workgroup.
+// inv(L11), inv(U11) of diagonal block b (in LDS, pitch NP_TP) to DI (all threads).
+__device__ __forceinline__ void np_copy_inverses(const double* IL, const double* IU, double* __restrict__ di, int b,
+                                                 int tid) {
+    for (int idx = tid; idx < 2 * NP_NB * NP_NB; idx += LW_NT) {
+        const int which = idx >> 10, r = (idx >> 5) & 31, c = idx & 31;
+        di[(size_t)b * DI_STRIDE + which * NP_NB * NP_NB + r * NP_NB + c] = (which ? IU : IL)[r * NP_TP + c];
+    }
+}
+
+// Rows [0, j0) of the block column at j0 of U (final U12 blocks of earlier
+// panels) times inv(U11) of the diagonal block at j0 (32 x 32, row-major in
+// global memory), in place; 16-row tasks k, k + nw, ... of this wave.
+__device__ __forceinline__ void np_scale_u(double* __restrict__ out, const double* __restrict__ iu, int M, int j0,
+                                           int g, int cc, int k, int nw) {
+    for (int q = k; q < j0 / 16; q += nw) {
+        const double* arow = out + (size_t)(16 * q + cc) * M + j0 + g;
+        double av[8], b0[8], b1[8];
+#pragma unroll
+        for (int kk = 0; kk < 8; ++kk) {
+            av[kk] = arow[4 * kk];
+            b0[kk] = iu[(4 * kk + g) * NP_NB + cc];
+            b1[kk] = iu[(4 * kk + g) * NP_NB + 16 + cc];
+        }
+        v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kk = 0; kk < 8; ++kk) {
+            acc0 = mfma4(av[kk], b0[kk], acc0);
+            acc1 = mfma4(av[kk], b1[kk], acc1);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            double* orow = out + (size_t)(16 * q + g + 4 * v) * M + j0;
+            orow[cc] = acc0[v];
+            orow[16 + cc] = acc1[v];
+        }
+    }
+}
+
 __device__ __forceinline__ bool getrf_nointerchange(const double* __restrict__ a, double* __restrict__ out, int* __restrict__ perm,
-                                    int M, char* smc) {
+                                    double* __restrict__ di, int M, char* smc) {
     constexpr NpLds lay = np_lds_layout();
     constexpr int TP = NP_TP, LPP = NP_LPP, UPP = NP_UPP;
     // array offsets kept in registers: every LDS access is then a register
@@ -1340,10 +1384,15 @@ __device__ __forceinline__ bool getrf_nointerchange(const double* __restrict__ a
             // (rows) of its block before it overwrites them (in place from the
             // second panel on), so no two tasks share a block
             bool okp = true;
-            // a task's eight operands per lane: a row piece of A21 (q < nt2) or
-            // a column piece of A12, addressed without a branch; the next
-            // task's operands are loaded before the current task's products
-            // (past the last task: the last one again, unused)
+            // tasks q < nt2: rows of A21; nt2 <= q < 2 nt2: columns of A12.
+            // A task's eight operands per lane (a row piece, or a column piece
+            // of A12) are addressed without a branch; the next task's
+            // operands are loaded before the current task's products (past
+            // the last task: the last one again, unused).  The block's
+            // inverses also go to DI (the rows of U above the block are
+            // scaled from there during the update phase).
+            const int nq = 2 * nt2;
+            np_copy_inverses(IL, IU, di, j0 / NP_NB, tid);
             auto tload = [&](int q, double (&x)[8]) {
                 const bool lt = q < nt2;
                 const double* base = lt ? src + (size_t)(j0 + NP_NB + 16 * q + cc) * M + j0 + g
@@ -1353,10 +1402,10 @@ __device__ __forceinline__ bool getrf_nointerchange(const double* __restrict__ a
                 for (int kk = 0; kk < 8; ++kk) x[kk] = base[kk * st];
             };
             double xv[8];
-            if (w < 2 * nt2) tload(w, xv);
-            for (int q = w; q < 2 * nt2; q += NW) {
+            if (w < nq) tload(w, xv);
+            for (int q = w; q < nq; q += NW) {
                 double xn[8];
-                tload(min(q + NW, 2 * nt2 - 1), xn);
+                tload(min(q + NW, nq - 1), xn);
                 v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
                 if (q < nt2) {
                     const double* av = xv;
@@ -1365,15 +1414,29 @@ __device__ __forceinline__ bool getrf_nointerchange(const double* __restrict__ a
                         acc0 = mfma4(av[kk], IU[(4 * kk + g) * TP + cc], acc0);
                         acc1 = mfma4(av[kk], IU[(4 * kk + g) * TP + 16 + cc], acc1);
                     }
+                    {
+                        // L21 to LP for the trailing update, L21 inv(L11) to out
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const int row = 16 * q + g + 4 * v;
-                        okp = okp && fabs(acc0[v]) <= 1.0 && fabs(acc1[v]) <= 1.0;
-                        double* orow = out + (size_t)(j0 + NP_NB + row) * M + j0;
-                        orow[cc] = acc0[v];
-                        orow[16 + cc] = acc1[v];
-                        LP[row * LPP + cc] = acc0[v];
-                        LP[row * LPP + 16 + cc] = acc1[v];
+                        for (int v = 0; v < 4; ++v) {
+                            const int row = 16 * q + g + 4 * v;
+                            okp = okp && fabs(acc0[v]) <= 1.0 && fabs(acc1[v]) <= 1.0;
+                            LP[row * LPP + cc] = acc0[v];
+                            LP[row * LPP + 16 + cc] = acc1[v];
+                        }
+                        wave_lds_sync();
+                        v4d s0 = {0.0, 0.0, 0.0, 0.0}, s1 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                        for (int kk = 0; kk < 8; ++kk) {
+                            const double l = LP[(16 * q + cc) * LPP + 4 * kk + g];
+                            s0 = mfma4(l, IL[(4 * kk + g) * TP + cc], s0);
+                            s1 = mfma4(l, IL[(4 * kk + g) * TP + 16 + cc], s1);
+                        }
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            double* orow = out + (size_t)(j0 + NP_NB + 16 * q + g + 4 * v) * M + j0;
+                            orow[cc] = s0[v];
+                            orow[16 + cc] = s1[v];
+                        }
                     }
                 } else {
                     const int u = q - nt2;
@@ -1419,13 +1482,28 @@ __device__ __forceinline__ bool getrf_nointerchange(const double* __restrict__ a
                 const int bt = kb / nb2, bu = kb - bt * nb2;
                 np_block(src, out, M, j0, g, cc, LP, UP, 2 * bt, 2 * bu);
             }
+            // the rows of U above the block at j0 scaled by its inv(U11)
+            // (read from DI: wave 0 is replacing the LDS copy), beside the
+            // diagonal block's factorisation
+            np_scale_u(out, di + (size_t)(j0 / NP_NB) * DI_STRIDE + NP_NB * NP_NB, M, j0, g, cc, w - 1, NW - 1);
         }
         __syncthreads();
         if (FL[0]) return false;
     }
+    // the last diagonal block: its inverses, and the rows of U above it scaled
+    {
+        const int jl = M - NP_NB;
+        np_copy_inverses(IL, IU, di, jl / NP_NB, tid);
+        __syncthreads();
+        int lv = lane;
+        __asm__ volatile("" : "+v"(lv));
+        np_scale_u(out, di + (size_t)(jl / NP_NB) * DI_STRIDE + NP_NB * NP_NB, M, jl, lv >> 4, lv & 15, w, NW);
+    }
     for (int q = tid; q < M; q += LW_NT) perm[q] = q;
     return true;
 }
+
+__device__ __noinline__ void diag_prep_row_lw(const Level& L, int i, double* lds);
 
 __global__ __launch_bounds__(LW_NT) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_getrf_pw(const KArgs ka) {
     constexpr int NB = LW_NB, P = LW_P;
@@ -1441,9 +1519,11 @@ __global__ __launch_bounds__(LW_NT) __attribute__((amdgpu_waves_per_eu(1, 2))) v
     int* perm = L.perm + (size_t)i * M;
     extern __shared__ double sm_raw[];
     char* smc = (char*)sm_raw;
-    // the case without row interchanges first; the factorisation with
-    // interchanges below when a check of it fails
-    if ((M & (NP_NB - 1)) == 0 && getrf_nointerchange(a, out, perm, M, smc)) return;
+    // the case without row interchanges first (it also prepares the factors
+    // for the triangular solves); the factorisation with interchanges below
+    // when a check of it fails
+    if ((M & (NP_NB - 1)) == 0 && getrf_nointerchange(a, out, perm, L.DI + (size_t)i * (M / DB) * DI_STRIDE, M, smc))
+        return;
     __syncthreads();   // its LDS is reused
     constexpr LwLds lay = lw_lds_layout();
     double* NX = (double*)(smc + lay.nx);
@@ -1719,6 +1799,12 @@ __global__ __launch_bounds__(LW_NT) __attribute__((amdgpu_waves_per_eu(1, 2))) v
         }
     }
     if (w == 0 && lane0 == 0 && fail_code != 0) report_status(ka.status, L.level, i, fail_col, fail_code);
+    // for M a multiple of 32 no separate preparation follows (the case
+    // without interchanges prepares its rows): prepare this row here
+    if ((M & (NP_NB - 1)) == 0) {
+        __syncthreads();   // the factors are written, the LDS is free
+        diag_prep_row_lw(L, i, sm_raw);
+    }
 }
 
 // Preparation of the factors of every D_i factored at this step for the
@@ -1733,19 +1819,16 @@ __global__ __launch_bounds__(LW_NT) __attribute__((amdgpu_waves_per_eu(1, 2))) v
 // before its diagonal solve, so no diagonal product sits on the sweep's
 // sequential chain: for L y = r, w_b = r_b - sum_{b'<b} Lt_{b,b'} w_{b'} and
 // y_b = inv(L_bb) w_b; likewise for U.
-__global__ __launch_bounds__(256) void k_diag_prep(const KArgs ka) {
-    const Level& L = ka.L;
-    const int k = ka.c0 + blockIdx.y, t = ka.step, M = L.M;
-    const int r0 = chunk_first(L, k), e = chunk_last(L, k);
-    if (t > e - r0) return;
-    const int i = r0 + t;
-    const int bb = blockIdx.x, b0 = bb * DB, bs = min(DB, M - b0);
+// Block column bb of row i (all NT threads; blk and inv: LDS of
+// DB (DB + 1) and 2 DB (DB + 1) doubles).
+template <int NT>
+__device__ __forceinline__ void diag_prep_block(const Level& L, int i, int bb, double* blk, double (*inv)[DB * (DB + 1)]) {
+    const int M = L.M;
+    const int b0 = bb * DB, bs = min(DB, M - b0);
     const int nblk = (M + DB - 1) / DB;
     double* a = L.LU + (size_t)i * M * M;
-    __shared__ double blk[DB * (DB + 1)];
-    __shared__ double inv[2][DB * (DB + 1)];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    for (int idx = tid; idx < DB * DB; idx += 256) {
+    for (int idx = tid; idx < DB * DB; idx += NT) {
         const int rr = idx / DB, cc = idx % DB;
         blk[rr * (DB + 1) + cc] = (rr < bs && cc < bs) ? a[(size_t)(b0 + rr) * M + b0 + cc] : 0.0;
     }
@@ -1779,7 +1862,7 @@ __global__ __launch_bounds__(256) void k_diag_prep(const KArgs ka) {
     }
     __syncthreads();
     // scale the off-diagonal blocks of this block column: 16-row strips, one wave each
-    for (int st = w; st < 2 * nblk; st += 4) {
+    for (int st = w; st < 2 * nblk; st += NT / 64) {
         if (st / 2 == bb) continue;
         const int which = (st / 2 > bb) ? 0 : 1;
         const int row0 = st * 16;
@@ -1808,6 +1891,28 @@ __global__ __launch_bounds__(256) void k_diag_prep(const KArgs ka) {
             }
         }
     }
+}
+
+// All block columns of row i from the LU kernel (its 512 threads, its LDS).
+__device__ __noinline__ void diag_prep_row_lw(const Level& L, int i, double* lds) {
+    double* blk = lds;
+    double (*inv)[DB * (DB + 1)] = (double (*)[DB * (DB + 1)])(lds + DB * (DB + 1));
+    for (int bb = 0; bb < L.M / DB; ++bb) {
+        diag_prep_block<LW_NT>(L, i, bb, blk, inv);
+        __syncthreads();
+    }
+}
+
+// One workgroup per (block column, chunk), for block sizes whose LU does not
+// prepare its rows itself (M not a multiple of 32, or above 256).
+__global__ __launch_bounds__(256) void k_diag_prep(const KArgs ka) {
+    const Level& L = ka.L;
+    const int k = ka.c0 + blockIdx.y, t = ka.step;
+    const int r0 = chunk_first(L, k), e = chunk_last(L, k);
+    if (t > e - r0) return;
+    __shared__ double blk[DB * (DB + 1)];
+    __shared__ double inv[2][DB * (DB + 1)];
+    diag_prep_block<256>(L, r0 + t, blockIdx.x, blk, inv);
 }
 
 // ------------------------------------------------------------------ triangular solves
@@ -3232,9 +3337,11 @@ hipError_t launch_getrf(const KArgs& ka, hipStream_t s) {
     return hipGetLastError();
 }
 
+bool lu_prepares(int M) { return M % DB == 0 && M <= 256; }
+
 hipError_t launch_diag_inv(const KArgs& ka, hipStream_t s) {
-    dim3 grid(cdiv(ka.L.M, DB), ka.nc);
-    hipLaunchKernelGGL(k_diag_prep, grid, dim3(256), 0, s, ka);
+    if (lu_prepares(ka.L.M)) return hipSuccess;   // the LU kernel prepared every row
+    hipLaunchKernelGGL(k_diag_prep, dim3(cdiv(ka.L.M, DB), ka.nc), dim3(256), 0, s, ka);
     return hipGetLastError();
 }
 

@@ -346,7 +346,7 @@ struct btd_plan_s {
 
     Level level_dev(int l) const {
         const LevelPlan& L = levels[l];
-        Level d;
+        Level d{};
         if (l == 0) { d.A = A; d.B = B; d.C = C; }
         else {
             const LevelPlan& up = levels[l - 1];
@@ -478,7 +478,7 @@ int enqueue_factor(btd_plan_s* p, hipStream_t s, FusedSolve* fs) {
                 gk[g].step = t;
                 BTD_TRY(timed(BTD_KC_FWD_GEMM, gs[g], btd::launch_fwd_gemm, gk[g]));
                 BTD_TRY(timed(BTD_KC_GETRF, gs[g], btd::launch_getrf, gk[g]));
-                BTD_TRY(timed(BTD_KC_DIAG_PREP, gs[g], btd::launch_diag_inv, gk[g]));
+                if (!btd::lu_prepares(LP.M)) BTD_TRY(timed(BTD_KC_DIAG_PREP, gs[g], btd::launch_diag_inv, gk[g]));
                 BTD_TRY(timed(BTD_KC_GETRS_FACTOR, gs[g], btd::launch_getrs, gk[g]));
             }
         }
