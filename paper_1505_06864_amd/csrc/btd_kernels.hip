@@ -1517,14 +1517,21 @@ __global__ __launch_bounds__(LW_NT) __attribute__((amdgpu_waves_per_eu(1, 2))) v
     double* a = L.Dw + (size_t)kch * M * M;      // working copy, rows in place
     double* out = L.LU + (size_t)i * M * M;      // factors, rows in pivot order
     int* perm = L.perm + (size_t)i * M;
+    // at a chunk's first row D_i = A_i: no forward product runs at that
+    // step, so the factorisation reads A_i itself (the pivoting path, which
+    // works in place, copies it into the working copy first)
+    const double* a_in = t == 0 ? L.A + (size_t)i * M * M : a;
     extern __shared__ double sm_raw[];
     char* smc = (char*)sm_raw;
     // the case without row interchanges first (it also prepares the factors
     // for the triangular solves); the factorisation with interchanges below
     // when a check of it fails
-    if ((M & (NP_NB - 1)) == 0 && getrf_nointerchange(a, out, perm, L.DI + (size_t)i * (M / DB) * DI_STRIDE, M, smc))
+    if ((M & (NP_NB - 1)) == 0 &&
+        getrf_nointerchange(a_in, out, perm, L.DI + (size_t)i * (M / DB) * DI_STRIDE, M, smc))
         return;
-    __syncthreads();   // its LDS is reused
+    if (t == 0)
+        for (int q = tid; q < M * M; q += LW_NT) a[q] = a_in[q];
+    __syncthreads();   // its LDS is reused (and the working copy complete)
     constexpr LwLds lay = lw_lds_layout();
     double* NX = (double*)(smc + lay.nx);
     double* LB = (double*)(smc + lay.lb);
@@ -2441,6 +2448,10 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
     // (the forward product does not copy it for this kernel); the solution
     // goes to W_i.
     const double* Ci = RHS ? X : L.C + (size_t)i * M * M;
+    // at a chunk's first row the Y half starts as B_i, read from B itself (no
+    // forward product runs at that step)
+    const bool seed = !RHS && t == 0;
+    const double* Bi = L.B + (size_t)i * M * M;
     V4 x[NBLK][2][NT16];
 #pragma unroll
     for (int b = 0; b < NBLK; ++b)
@@ -2454,9 +2465,10 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
                 const int col = c0 + 16 * nt + j;
                 const bool cv = col < e_hi || (col >= M && col < y_hi);
                 const bool fromC = !RHS && cv && col < M;
-                const double* src = fromC ? Ci : X;
-                const int lds = fromC ? M : ld;
-                const int cs = cv ? col : 0;
+                const bool fromB = seed && cv && col >= M;
+                const double* src = fromC ? Ci : fromB ? Bi : X;
+                const int lds = (fromC || fromB) ? M : ld;
+                const int cs = !cv ? 0 : fromB ? col - M : col;
 #pragma unroll
                 for (int v = 0; v < 4; ++v) x[b][tr][nt][v] = (CT)src[(uint32_t)(prw[v] * lds + cs)];
             }

@@ -476,7 +476,8 @@ int enqueue_factor(btd_plan_s* p, hipStream_t s, FusedSolve* fs) {
         for (int t = 0; t < LP.nmax; ++t) {
             for (int g = 0; g < G; ++g) {
                 gk[g].step = t;
-                BTD_TRY(timed(BTD_KC_FWD_GEMM, gs[g], btd::launch_fwd_gemm, gk[g]));
+                if (t > 0 || !btd::first_step_reads_inputs(LP.M))
+                    BTD_TRY(timed(BTD_KC_FWD_GEMM, gs[g], btd::launch_fwd_gemm, gk[g]));
                 BTD_TRY(timed(BTD_KC_GETRF, gs[g], btd::launch_getrf, gk[g]));
                 if (!btd::lu_prepares(LP.M)) BTD_TRY(timed(BTD_KC_DIAG_PREP, gs[g], btd::launch_diag_inv, gk[g]));
                 BTD_TRY(timed(BTD_KC_GETRS_FACTOR, gs[g], btd::launch_getrs, gk[g]));
