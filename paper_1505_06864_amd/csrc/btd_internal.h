@@ -48,9 +48,10 @@ struct IntChunk {
 
 enum GemmMode { GM_FWD = 0, GM_BWD, GM_COUPLE, GM_COUPLE_RHS, GM_RECOVER, GM_RHS_FWD, GM_RHS_BWD };
 
-// For M <= 256 the first step of a chunk runs no forward product: its LU
-// reads A_i and its slab solve reads B_i (the seed of the left spike)
-// directly.
+// For M <= 256 the first step of a chunk runs no forward product (its LU
+// reads A_i and its slab solve reads B_i, the seed of the left spike,
+// directly) and the backward sweep no first step (the slab solve of a
+// chunk's last row writes that row's spikes Z_e = [Y_e | E_e] itself).
 inline bool first_step_reads_inputs(int M) { return M <= 256; }
 hipError_t launch_fwd_gemm(const KArgs& ka, hipStream_t s);
 hipError_t launch_bwd_gemm(const KArgs& ka, hipStream_t s);

@@ -2491,6 +2491,11 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
     tseq_stage<NBLK, PC, CT>(1, ring + TS_BLOCK, tid, p1, m1);
     __syncthreads();
     tseq_run2<NBLK, NT16, PC, 0, CT>(x, ring, lu, di, M, nblk, tid, lane, p2, m2, p3, m3, p4, m4, p5, m5);
+    // at a chunk's last row the spikes start the backward sweep as they
+    // are: Z_e = [Z_L | Z_R] = [Y_e | E_e], written here as well (the
+    // backward sweep runs no step for that row)
+    const bool zlast = !RHS && L.P > 1 && i == e;
+    double* Ze = L.Z + (size_t)i * M * 2 * M;
 #pragma unroll
     for (int b = 0; b < NBLK; ++b)
 #pragma unroll
@@ -2499,9 +2504,11 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPE)))
             for (int nt = 0; nt < NT16; ++nt) {
                 const int col = c0 + 16 * nt + j;
                 const bool cv = col < e_hi || (col >= M && col < y_hi);
+                const int zc = col < M ? col + M : col - M;
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int row = b * DB + 8 * g + 4 * tr + v;
+                    if (cv && row < M && zlast) Ze[(uint32_t)(row * 2 * M + zc)] = (double)x[b][tr][nt][v];
                     if (cv && row < M) X[(uint32_t)(row * ld + col)] = (double)x[b][tr][nt][v];
                 }
             }

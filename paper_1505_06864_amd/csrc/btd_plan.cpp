@@ -503,7 +503,10 @@ int enqueue_factor(btd_plan_s* p, hipStream_t s, FusedSolve* fs) {
             for (int t = 0; t < LP.nmax; ++t)
                 for (int g = 0; g < G; ++g) {
                     gk[g].step = t;
-                    BTD_TRY(timed(BTD_KC_BWD_GEMM, gs[g], btd::launch_bwd_gemm, gk[g]));
+                    // the first backward step only copies the spikes of each chunk's
+                    // last row, which the slab solve wrote already (M <= 256)
+                    if (t > 0 || !btd::first_step_reads_inputs(LP.M))
+                        BTD_TRY(timed(BTD_KC_BWD_GEMM, gs[g], btd::launch_bwd_gemm, gk[g]));
                 }
         }
         if (G > 1) {
