@@ -45,7 +45,7 @@ def check_case(torch, A, B, C, F, P, depth=0, seps=None, inplace=False, coupling
     return X
 
 
-@pytest.mark.parametrize("N,M,R", [(1, 4, 1), (9, 16, 3), (64, 33, 2), (5, 256, 1),
+@pytest.mark.parametrize("N,M,R", [(1, 4, 1), (9, 16, 3), (64, 33, 2), (5, 256, 1), (1, 256, 1), (3, 512, 1),
                                    (1, 16, 8), (9, 16, 8), (5, 256, 64), (7, 33, 70), (3, 130, 9)])
 def test_residual_kernel_matches_oracle(N, M, R):
     """The device residual of a perturbed solution (residual well above
