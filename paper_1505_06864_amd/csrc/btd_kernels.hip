@@ -1503,7 +1503,7 @@ __device__ __forceinline__ bool getrf_nointerchange(const double* __restrict__ a
     return true;
 }
 
-__device__ __noinline__ void diag_prep_row_lw(const Level& L, int i, double* lds);
+__device__ void diag_prep_row_lw(const Level& L, int i, double* lds);
 
 __global__ __launch_bounds__(LW_NT) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_getrf_pw(const KArgs ka) {
     constexpr int NB = LW_NB, P = LW_P;
@@ -1901,9 +1901,13 @@ __device__ __forceinline__ void diag_prep_block(const Level& L, int i, int bb, d
 }
 
 // All block columns of row i from the LU kernel (its 512 threads, its LDS).
-__device__ __noinline__ void diag_prep_row_lw(const Level& L, int i, double* lds) {
-    double* blk = lds;
-    double (*inv)[DB * (DB + 1)] = (double (*)[DB * (DB + 1)])(lds + DB * (DB + 1));
+__device__ __forceinline__ void diag_prep_row_lw(const Level& L, int i, double* lds) {
+    // the LDS offsets held in registers (not one scalar constant per access)
+    int o1 = 0, o2 = DB * (DB + 1);
+    __asm__ volatile("" : "+v"(o1), "+v"(o2));
+    double* blk = lds + o1;
+    double (*inv)[DB * (DB + 1)] = (double (*)[DB * (DB + 1)])(lds + o2);
+#pragma nounroll
     for (int bb = 0; bb < L.M / DB; ++bb) {
         diag_prep_block<LW_NT>(L, i, bb, blk, inv);
         __syncthreads();
