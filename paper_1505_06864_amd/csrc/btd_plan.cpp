@@ -446,6 +446,7 @@ int enqueue_factor_solve(btd_plan_s* p, int R, const double* F, double* X, char*
 
 int enqueue_factor(btd_plan_s* p, hipStream_t s, FusedSolve* fs) {
     BTD_TRY(btd::launch_init_status(p->status, s));
+    bool deeper_tables = false;  // separator tables of levels 1.. already enqueued
     for (size_t l = 0; l < p->levels.size(); ++l) {
         const LevelPlan& LP = p->levels[l];
         KArgs ka;
@@ -455,7 +456,8 @@ int enqueue_factor(btd_plan_s* p, hipStream_t s, FusedSolve* fs) {
         ka.c0 = 0;
         ka.nc = LP.P;
         ka.lowp = (p->desc.prec == BTD_PREC_F32_REFINE && l == 0) ? 1 : 0;
-        BTD_TRY(btd::launch_write_ints((int*)(p->ws + LP.off_sep), LP.sep.data(), LP.P + 1, s));
+        if (l == 0 || !deeper_tables)
+            BTD_TRY(btd::launch_write_ints((int*)(p->ws + LP.off_sep), LP.sep.data(), LP.P + 1, s));
         // chunk groups, each on its own stream (one group: the caller's stream);
         // with a fused solve the last side stream belongs to the right-hand side
         int G = std::min(chunk_groups(LP.P), fs ? kMaxGroups - 1 : kMaxGroups);
@@ -472,6 +474,15 @@ int enqueue_factor(btd_plan_s* p, hipStream_t s, FusedSolve* fs) {
         if (G > 1) {
             BTD_TRY(hipEventRecord(pool.fork, s));
             for (int g = 0; g < G; ++g) BTD_TRY(hipStreamWaitEvent(gs[g], pool.fork, 0));
+            // the caller's stream idles until the groups join: the deeper levels'
+            // tables are written there meanwhile instead of ahead of each level
+            if (l == 0) {
+                for (size_t ll = 1; ll < p->levels.size(); ++ll) {
+                    const LevelPlan& LQ = p->levels[ll];
+                    BTD_TRY(btd::launch_write_ints((int*)(p->ws + LQ.off_sep), LQ.sep.data(), LQ.P + 1, s));
+                }
+                deeper_tables = true;
+            }
         }
         for (int t = 0; t < LP.nmax; ++t) {
             for (int g = 0; g < G; ++g) {
